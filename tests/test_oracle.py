@@ -1,0 +1,321 @@
+"""Pins for the CPU oracle: checks against things other than the oracle itself.
+
+* the cyclic-embedding identity (Section 2.2, step 5): the FFT route equals the
+  direct O(N^6) sum, which in turn equals six plain loops on tiny grids;
+* the DFT = DCT-I identity of Section 2.4: three independent routes to the
+  Vico-Greengard kernel agree; the transform of the mirror kernel is real and
+  even;
+* the paper's accuracy table (Table 3) and convergence claims (Section 3.1);
+* exact invariants: linearity, translation, reflection symmetry, and the
+  irrelevance of the mirror value K[N];
+* closed forms checked by a finite-difference Laplacian;
+* the memory formulas against Table 2.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.fft
+
+import oracle
+import workloads as W
+from oracle import direct, exact, fftroute, greens, memory
+
+UNIT = ((-0.5,) * 3, (0.5,) * 3)
+
+
+def _kernel(kind, n, lo, hi):
+    if kind == "hockney":
+        return greens.hockney_octant(n, lo, hi)
+    if kind == "vico":
+        return greens.vico_octant_4n(n, lo, hi)
+    return greens.vico_octant(n, lo, hi)
+
+
+# ---------------------------------------------------------------- definition
+def test_direct_matches_six_loops():
+    rng = np.random.default_rng(11)
+    n = (3, 4, 5)
+    k = rng.standard_normal((4, 5, 6))
+    rho = rng.standard_normal(n)
+    h = (0.3, 0.2, 0.1)
+    a = direct.convolve(rho, k, h)
+    b = direct.convolve_loops(rho, k, h)
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+
+
+def test_direct_at_matches_direct():
+    rng = np.random.default_rng(12)
+    n = (6, 5, 7)
+    k = rng.standard_normal((7, 6, 8))
+    rho = rng.standard_normal(n)
+    h = (0.1, 0.2, 0.3)
+    full = direct.convolve(rho, k, h)
+    pts = [(0, 0, 0), (5, 4, 6), (2, 3, 1), (5, 0, 3)]
+    got = direct.convolve_at(rho, k, h, pts)
+    assert np.allclose(got, [full[p] for p in pts], rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("kind", ["hockney", "vico_dct"])
+@pytest.mark.parametrize("n,lo,hi", [
+    (8, (-0.5,) * 3, (0.5,) * 3),
+    ((6, 10, 12), (-1.0, -1.0, -2.0), (1.0, 1.0, 2.0)),
+    ((16, 8, 12), (0.0, 0.0, 0.0), (1.0, 0.5, 0.75)),
+])
+def test_fft_route_equals_direct_sum(kind, n, lo, hi):
+    """Section 2.2 step 5: the cyclic convolution restricted to the box is the aperiodic one."""
+    h = greens.spacing(n, lo, hi)
+    k = _kernel(kind, n, lo, hi)
+    for seed in (1, 2):
+        rho = W.random_field(n, seed)
+        ref = direct.convolve(rho, k, h)
+        got = fftroute.solve(rho, k, h)
+        assert oracle.rel_l2(got, ref) < 1e-13
+
+
+@pytest.mark.slow
+def test_fft_route_equals_direct_sum_32():
+    n = 32
+    h = greens.spacing(n, *UNIT)
+    k = greens.hockney_octant(n, *UNIT)
+    rho = W.source_density(n, *UNIT, W.centred_gaussian(0.05))
+    assert oracle.rel_l2(fftroute.solve(rho, k, h), direct.convolve(rho, k, h)) < 1e-13
+
+
+def test_mirror_value_is_irrelevant():
+    """Offsets |i - j| <= N - 1 never reach the mirror value K[N] (reading of step 3)."""
+    n = (8, 6, 10)
+    lo, hi = (-1.0,) * 3, (1.0,) * 3
+    h = greens.spacing(n, lo, hi)
+    k = greens.hockney_octant(n, lo, hi)
+    rho = W.random_field(n, 5)
+    base = fftroute.solve(rho, k, h)
+    k2 = k.copy()
+    k2[-1, :, :] += 3.0
+    k2[:, -1, :] -= 7.0
+    k2[:, :, -1] *= 5.0
+    assert oracle.rel_l2(fftroute.solve(rho, k2, h), base) < 1e-14
+    assert oracle.rel_l2(direct.convolve(rho, k2, h), base) < 1e-13
+
+
+# ------------------------------------------------------------ kernel tables
+@pytest.mark.parametrize("n,lo,hi", [
+    (8, (-0.5,) * 3, (0.5,) * 3),
+    (16, (-0.5,) * 3, (0.5,) * 3),
+    ((8, 12, 16), (-1.0, -1.0, -2.0), (1.0, 1.0, 2.0)),
+])
+def test_vico_three_routes_agree(n, lo, hi):
+    """Section 2.4: DCT-I on (2N+1)^3 == inverse FFT on (4N)^3, restricted."""
+    a = greens.vico_octant(n, lo, hi)
+    b = greens.vico_octant_dct(n, lo, hi)
+    c = greens.vico_octant_4n(n, lo, hi)
+    scale = np.max(np.abs(c))
+    assert np.max(np.abs(a - c)) <= 1e-14 * scale
+    assert np.max(np.abs(b - c)) <= 1e-14 * scale
+
+
+def test_vico_4n_grid_is_real():
+    """The 4N inverse transform of an even real spectrum is real (Section 2.4)."""
+    n, lo, hi = 8, (-0.5,) * 3, (0.5,) * 3
+    h = greens.spacing(n, lo, hi)
+    L = greens.vico_length(lo, hi)
+    k = [2 * np.pi * np.fft.fftfreq(4 * n, d=1.0 / (4 * n)) / (4 * n * h[d]) for d in range(3)]
+    kk = np.sqrt(k[0][:, None, None] ** 2 + k[1][None, :, None] ** 2 + k[2][None, None, :] ** 2)
+    g = np.where(kk > 0, 2 * (np.sin(L * kk / 2) / np.where(kk > 0, kk, 1)) ** 2, L * L / 2)
+    x = np.fft.ifftn(g)
+    assert np.max(np.abs(x.imag)) <= 1e-15 * np.max(np.abs(x.real))
+
+
+def test_vico_spectrum_limit_and_form():
+    """eq. (3) at k = 0 is its limit L^2/2; elsewhere 2 sin^2(L|k|/2)/|k|^2 = (1 - cos L|k|)/|k|^2."""
+    n, lo, hi = 8, (-1.0,) * 3, (1.0,) * 3
+    g = greens.vico_spectrum(n, lo, hi, alpha=1.1)
+    L = greens.vico_length(lo, hi, 1.1)
+    assert L == pytest.approx(1.1 * np.sqrt(12.0), rel=1e-15)
+    assert g[0, 0, 0] == pytest.approx(L * L / 2, rel=1e-15)
+    h = greens.spacing(n, lo, hi)
+    kx = np.pi * 3 / (2 * n * h[0])
+    assert g[3, 0, 0] == pytest.approx((1 - np.cos(L * kx)) / kx ** 2, rel=1e-12)
+    # sinc behaviour near zero: continuous
+    assert g[1, 0, 0] < g[0, 0, 0]
+
+
+def test_hockney_kernel_values():
+    n, lo, hi = (4, 6, 8), (0.0, 0.0, 0.0), (1.0, 3.0, 2.0)
+    k = greens.hockney_octant(n, lo, hi)
+    h = greens.spacing(n, lo, hi)
+    assert k.shape == (5, 7, 9)
+    assert k[0, 0, 0] == pytest.approx(1 / (4 * np.pi))
+    assert k[2, 1, 3] == pytest.approx(1 / (4 * np.pi * np.sqrt((2 * h[0]) ** 2 + h[1] ** 2 + (3 * h[2]) ** 2)))
+    assert greens.hockney_octant(n, lo, hi, g0=0.0)[0, 0, 0] == 0.0
+
+
+@pytest.mark.parametrize("kind", ["hockney", "vico_dct"])
+def test_mirror_transform_is_real_even_dct(kind):
+    """Steps 3-4: the DFT of the mirror-extended kernel is real and even, and equals
+    the DCT-I octant computed with cosine matrices."""
+    n, lo, hi = (8, 6, 12), (-1.0, -1.0, -2.0), (1.0, 1.0, 2.0)
+    k = _kernel(kind, n, lo, hi)
+    g2 = greens.mirror_extend(k)
+    full = np.fft.fftn(g2)
+    scale = np.max(np.abs(full))
+    assert np.max(np.abs(full.imag)) <= 1e-14 * scale
+    oct_ = greens.mirror_transform_octant(k)
+    assert np.max(np.abs(full.real[:9, :7, :13] - oct_)) <= 1e-14 * scale
+    # evenness: Ghat2[k] = Ghat2[M - k]
+    rev = full.real[(-np.arange(16)) % 16][:, (-np.arange(12)) % 12][:, :, (-np.arange(24)) % 24]
+    assert np.max(np.abs(rev - full.real)) <= 1e-14 * scale
+    # scipy DCT-I of the octant is the same transform
+    assert np.max(np.abs(scipy.fft.dctn(k, type=1) - oct_)) <= 1e-14 * scale
+
+
+# ---------------------------------------------------- paper accuracy pins
+def _golden_accuracy(golden_dir):
+    rows = []
+    with open(os.path.join(golden_dir, "accuracy_table.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                m, acc, grid = line.split()
+                rows.append((m, float(acc), int(grid)))
+    return rows
+
+
+def test_paper_accuracy_table(golden_dir):
+    """Table 3: each listed grid reaches the listed accuracy to within a factor of 10."""
+    lo, hi = UNIT
+    src = W.centred_gaussian(0.05)
+    checked = 0
+    for method, acc, n in _golden_accuracy(golden_dir):
+        if n > 128 or (method != "hockney" and n > 64):
+            continue
+        h = greens.spacing(n, lo, hi)
+        k = _kernel(method, n, lo, hi)
+        rho = W.source_density(n, lo, hi, src)
+        err = oracle.rel_l2(fftroute.solve(rho, k, h), exact.source_potential(n, lo, hi, src))
+        assert acc / 10 <= err <= acc * 10, (method, n, err, acc)
+        checked += 1
+    assert checked == 9
+
+
+def test_hockney_second_order():
+    """Section 2.2 / 3.1: Hockney-Eastwood converges at second order."""
+    lo, hi = UNIT
+    src = W.centred_gaussian(0.05)
+    errs = []
+    for n in (16, 32, 64):
+        h = greens.spacing(n, lo, hi)
+        rho = W.source_density(n, lo, hi, src)
+        errs.append(oracle.rel_l2(fftroute.solve(rho, greens.hockney_octant(n, lo, hi), h),
+                                  exact.source_potential(n, lo, hi, src)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((orders > 1.8) & (orders < 2.2)), (errs, orders)
+
+
+def test_vico_spectral_convergence():
+    """Section 3.1: spectral convergence for the smooth Gaussian, also off centre."""
+    lo, hi = UNIT
+    for src, e32_max in ((W.centred_gaussian(0.05), 1e-8), (W.offcentre_gaussian(), 1e-4)):
+        errs = []
+        for n in (16, 32, 64):
+            h = greens.spacing(n, lo, hi)
+            rho = W.source_density(n, lo, hi, src)
+            errs.append(oracle.rel_l2(fftroute.solve(rho, greens.vico_octant(n, lo, hi), h),
+                                      exact.source_potential(n, lo, hi, src)))
+        assert errs[1] < e32_max
+        assert errs[2] < 1e-10
+        # faster than any fixed order: the 32 -> 64 gain exceeds 2^8
+        assert errs[1] / errs[2] > 2 ** 8 or errs[2] < 1e-14
+
+
+def test_sphere_both_second_order():
+    """Section 3.1 (non-smooth source, eq. (5)): both kernels converge only at ~second order.
+
+    Box of side 2.4 with the unit ball at its centre, as in the paper (density 1
+    instead of 4 pi G: the problem is linear).  A ball sampled on a grid
+    converges irregularly, so the order is a least-squares slope over six sizes,
+    and Vico-Greengard is required to be no better than Hockney-Eastwood by more
+    than a small factor."""
+    lo, hi = (-1.2,) * 3, (1.2,) * 3
+    src = W.Source(balls=(((0.0, 0.0, 0.0), 1.0, 1.0),))
+    sizes = (16, 24, 32, 48, 64, 96)
+    errs = {"hockney": [], "vico_dct": []}
+    for n in sizes:
+        h = greens.spacing(n, lo, hi)
+        rho = W.source_density(n, lo, hi, src)
+        ex = exact.source_potential(n, lo, hi, src)
+        for kind in errs:
+            errs[kind].append(oracle.rel_l2(fftroute.solve(rho, _kernel(kind, n, lo, hi), h), ex))
+    for kind, e in errs.items():
+        slope = -np.polyfit(np.log(sizes), np.log(e), 1)[0]
+        assert 1.5 < slope < 3.0, (kind, e, slope)
+    ratio = np.array(errs["vico_dct"]) / np.array(errs["hockney"])
+    assert np.all(ratio > 0.2), ratio
+
+
+def test_closed_forms_satisfy_poisson():
+    """-Laplace(phi_exact) = rho at interior points (7-point stencil, h^2 accuracy)."""
+    n, lo, hi = 64, (-0.5,) * 3, (0.5,) * 3
+    h = greens.spacing(n, lo, hi)[0]
+    src = W.Source(blobs=(W.Blob((0.013, -0.021, 0.007), 0.1, 1.3),))
+    phi = exact.source_potential(n, lo, hi, src)
+    rho = W.source_density(n, lo, hi, src)
+    lap = (phi[2:, 1:-1, 1:-1] + phi[:-2, 1:-1, 1:-1] + phi[1:-1, 2:, 1:-1] + phi[1:-1, :-2, 1:-1]
+           + phi[1:-1, 1:-1, 2:] + phi[1:-1, 1:-1, :-2] - 6 * phi[1:-1, 1:-1, 1:-1]) / h ** 2
+    assert oracle.rel_l2(-lap, rho[1:-1, 1:-1, 1:-1]) < 5e-3
+    # sphere: constant Laplacian inside, zero outside (away from the surface)
+    ph = exact.sphere_potential(n, (-1.2,) * 3, (1.2,) * 3, (0, 0, 0), 1.0, 2.0)
+    hs = 2.4 / n
+    i = n // 2
+    lap_in = (ph[i + 1, i, i] + ph[i - 1, i, i] + ph[i, i + 1, i] + ph[i, i - 1, i] + ph[i, i, i + 1]
+              + ph[i, i, i - 1] - 6 * ph[i, i, i]) / hs ** 2
+    assert -lap_in == pytest.approx(2.0, rel=1e-10)
+
+
+# ----------------------------------------------------------- invariants
+def test_linearity_translation_symmetry():
+    n, lo, hi = 16, (-1.0,) * 3, (1.0,) * 3
+    h = greens.spacing(n, lo, hi)
+    k = greens.vico_octant(n, lo, hi)
+    a = W.random_field(n, 21)
+    b = W.random_field(n, 22)
+    pa, pb = fftroute.solve(a, k, h), fftroute.solve(b, k, h)
+    assert oracle.rel_l2(fftroute.solve(2.0 * a - 3.0 * b, k, h), 2.0 * pa - 3.0 * pb) < 1e-14
+    # translation by one cell along axis 1: exact for outputs whose offsets stay on the grid
+    s = np.zeros_like(a)
+    s[:, 1:, :] = a[:, :-1, :]
+    a0 = a.copy()
+    a0[:, -1, :] = 0.0
+    ps, p0 = fftroute.solve(s, k, h), fftroute.solve(a0, k, h)
+    assert np.max(np.abs(ps[:, 1:, :] - p0[:, :-1, :])) <= 1e-14 * np.max(np.abs(p0))
+    # a source symmetric under reflection of axis 2 gives a symmetric potential
+    c = a + a[:, :, ::-1]
+    pc = fftroute.solve(c, k, h)
+    assert np.max(np.abs(pc - pc[:, :, ::-1])) <= 1e-14 * np.max(np.abs(pc))
+
+
+def test_float32_route_error_is_small():
+    """The float32 FFT route stays near float32 rounding (context for the GPU bound)."""
+    n = 32
+    lo, hi = UNIT
+    h = greens.spacing(n, lo, hi)
+    k = greens.vico_octant(n, lo, hi)
+    rho = W.source_density(n, lo, hi, W.multiblob(3))
+    ref = fftroute.solve(rho, k, h)
+    got = fftroute.solve(rho.astype(np.float32), k, h, dtype=np.float32)
+    assert oracle.rel_l2(got, ref) < 1e-6
+
+
+# ------------------------------------------------------------- memory
+def test_memory_formulas_match_table2(golden_dir):
+    fn = {"hockney": memory.hockney_bytes, "vico": memory.vico_bytes, "vico_dct": memory.vico_dct_bytes}
+    rows = 0
+    with open(os.path.join(golden_dir, "memory_table.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            m, n, gb, tol = line.split()
+            assert abs(fn[m](int(n)) / 1e9 - float(gb)) <= float(tol), (m, n)
+            rows += 1
+    assert rows == 5
