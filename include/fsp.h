@@ -1,0 +1,156 @@
+/*
+ * fsp.h -- free-space Poisson solver for AMD Instinct MI355X (gfx950), C ABI.
+ *
+ * The library solves  -Laplace(phi) = rho  on a regular 3D grid with
+ * free-space (open) boundaries by the FFT convolution of the paper
+ * "A Massively Parallel Performance Portable Free-space Spectral Poisson
+ * Solver" (arXiv 2405.02603):
+ *
+ *   Section 2.2 (Hockney-Eastwood): double the grid, zero-pad rho, transform,
+ *   multiply by the transform of the mirror-extended Green's function,
+ *   transform back, restrict to the physical box;
+ *   Section 2.3, eq. (3) (Vico-Greengard): the same solve with the transform of
+ *   the truncated kernel 2 (sin(L|k|/2)/|k|)^2 precomputed on the 4N grid;
+ *   Section 2.4 (modified Vico-Greengard): that precompute done as a DCT-I on
+ *   the (2N+1)^3 unique samples.
+ *
+ * Discrete result.  With cell-centred points x_i = lo + (i + 1/2) h,
+ * h_d = (hi_d - lo_d) / n_d and V = h0 h1 h2, every solve computes
+ *
+ *     phi_i = V * sum_j K[|i0-j0|, |i1-j1|, |i2-j2|] * rho_j
+ *
+ * (the sum of eq. (2) over the grid) where K is the kernel of the chosen
+ * Green's function.  Units: epsilon_0 = 1, G = +1/(4 pi r).
+ *
+ * Arrays.  rho and phi are C-contiguous [n0][n1][n2] arrays of float
+ * (FSP_F32) or double (FSP_F64) in device memory, axis 2 fastest.
+ *
+ * Threads and streams.  A plan holds one workspace: at most one solve per
+ * plan may be in flight at a time.  Calls on different plans may run
+ * concurrently on different streams.  "stream" arguments are hipStream_t
+ * values passed as void*; NULL means the null stream.
+ *
+ * Errors.  Every call returns an fsp_status; nothing aborts and no C++
+ * exception crosses this boundary.  Argument errors are detected before
+ * anything is enqueued.  Errors of earlier asynchronous device work surface as
+ * FSP_ERR_DEVICE at a later call.  fsp_last_error() gives a per-thread text.
+ */
+#ifndef FSP_H_
+#define FSP_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsp_plan_s* fsp_plan;
+
+typedef enum {
+  FSP_OK = 0,
+  FSP_ERR_INVALID_ARG = 1,      /* NULL pointer, bad enum, lo >= hi, ...                 */
+  FSP_ERR_UNSUPPORTED_SIZE = 2, /* an n_d outside {2^a, 3*2^a : 8 <= n_d <= 512}         */
+  FSP_ERR_BOX_ASPECT = 3,       /* Vico-Greengard window too long for the 4N grid        */
+  FSP_ERR_OUT_OF_MEMORY = 4,    /* a device allocation failed                            */
+  FSP_ERR_NOT_READY = 5,        /* solve before bind/precompute                           */
+  FSP_ERR_DEVICE = 6            /* a HIP runtime call or kernel launch failed             */
+} fsp_status;
+
+/* Green's function.  The names follow the paper's three solver types. */
+typedef enum {
+  FSP_HOCKNEY = 0,   /* Section 2.2: K = 1/(4 pi |m h|), K[0] = g0                       */
+  FSP_VICO = 1,      /* Section 2.3: kernel by a (4N)^3 inverse FFT, restricted          */
+  FSP_VICO_DCT = 2   /* Section 2.4: the same kernel by a DCT-I on (2N+1)^3 samples       */
+} fsp_greens;
+
+typedef enum { FSP_F32 = 0, FSP_F64 = 1 } fsp_prec;
+
+/* Plan flags. */
+#define FSP_FLAG_NONE 0u
+
+typedef struct {
+  int n[3];          /* grid points per axis; axis 2 is contiguous                     */
+  double lo[3];      /* box lower corner                                                */
+  double hi[3];      /* box upper corner (hi_d > lo_d)                                  */
+  int greens;        /* fsp_greens                                                      */
+  int prec;          /* fsp_prec: precision of rho, phi and the solve passes            */
+  double alpha;      /* Vico-Greengard window factor, L = alpha |hi - lo|; 0 -> 1.1     */
+  double g0;         /* Hockney-Eastwood K[0]; NaN -> 1/(4 pi)                           */
+  unsigned flags;    /* FSP_FLAG_*                                                      */
+} fsp_plan_desc;
+
+/* Validate a descriptor and build a plan.  Host only: no device memory is
+ * touched.  Vico-Greengard plans are rejected with FSP_ERR_BOX_ASPECT when
+ * alpha * |hi - lo| > 3 * min_d (hi_d - lo_d): the periodic images of the
+ * truncated kernel on the 4N grid would then reach into the box (the paper
+ * states the 4N grid size, Section 2.3, but not this limit).
+ * On success *out owns a new plan; destroy it with fsp_plan_destroy. */
+fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out);
+
+/* Device bytes the plan needs: *ghat_bytes for the precomputed transform of
+ * the Green's function (plus the plan's twiddle tables), *work_bytes for the
+ * solve workspace.  Either pointer may be NULL. */
+fsp_status fsp_plan_bytes(fsp_plan p, size_t* ghat_bytes, size_t* work_bytes);
+
+/* Device bytes fsp_precompute needs transiently (freed before it returns to
+ * the caller's stream order); reported for admission control. */
+fsp_status fsp_plan_precompute_bytes(fsp_plan p, size_t* bytes);
+
+/* Attach device memory.  ghat_dev / work_dev are caller-owned device buffers
+ * of at least the sizes from fsp_plan_bytes, aligned to 256 bytes; NULL makes
+ * the plan allocate (and later free) that buffer itself.  Binding again
+ * replaces the previous buffers (a plan-owned buffer is freed) and clears the
+ * precompute state.  The current HIP device is the plan's device. */
+fsp_status fsp_plan_bind(fsp_plan p, void* ghat_dev, void* work_dev);
+
+/* Use src's precomputed transform in dst (same Green's function, grid, box,
+ * alpha, g0 and precision, else FSP_ERR_INVALID_ARG).  dst then reads src's
+ * buffer: src's Green's buffer must stay alive and unchanged while dst is used. */
+fsp_status fsp_plan_share_ghat(fsp_plan dst, fsp_plan src);
+
+/* Compute the transform of the Green's function on the device, in float64,
+ * and store it (rounded once to the solve precision) in the plan's Green's
+ * buffer, with the plan's twiddle tables.  Asynchronous on `stream`;
+ * allocates and frees a transient float64 buffer of
+ * fsp_plan_precompute_bytes bytes.  Calling it again recomputes. */
+fsp_status fsp_precompute(fsp_plan p, void* stream);
+
+/* phi = the free-space solution for rho (both device arrays, [n0][n1][n2] in
+ * the plan's precision).  phi may equal rho (in place; Section 3.3 reuses the
+ * rho field for phi).  Asynchronous on `stream`; enqueues five kernels and
+ * allocates nothing.  FSP_ERR_NOT_READY before bind + precompute. */
+fsp_status fsp_solve(fsp_plan p, const void* rho, void* phi, void* stream);
+
+/* count independent solves (each with its own plan, and so its own
+ * workspace) enqueued on one stream; plans may differ in size, precision and
+ * Green's function.  rho[i] / phi[i] as in fsp_solve.  Solves of plans with
+ * equal shape and precision are issued as shared kernel launches. */
+fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const* rho,
+                             void* const* phi, void* stream);
+
+/* Free the plan and any buffer it allocated.  Caller-owned buffers are not
+ * touched.  Work still queued on a stream must finish first. */
+fsp_status fsp_plan_destroy(fsp_plan p);
+
+/* Where the transform of the Green's function sits in the Green's buffer:
+ * *octant_offset is the byte offset of element [0][0][0] of a
+ * [n0+1][n1+1][*pitch] array of the solve precision holding the octant
+ * k in [0,n] (scaled by V / (8 n0 n1 n2)); elements k2 > n2 of a row are
+ * padding.  Either pointer may be NULL. */
+fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* pitch);
+
+/* Model bytes that one solve moves through HBM with this plan's schedule
+ * (reads + writes of the five passes, the Green's octant included). */
+fsp_status fsp_plan_model_bytes(fsp_plan p, double* bytes);
+
+const char* fsp_status_str(fsp_status s);
+const char* fsp_last_error(void);
+
+/* Library version string, e.g. "fsp 0.1.0 gfx950". */
+const char* fsp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSP_H_ */

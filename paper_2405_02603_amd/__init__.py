@@ -1,0 +1,223 @@
+"""Free-space Poisson solver on MI355X (gfx950): Python binding of libfsp.so.
+
+This module marshals arguments only.  Every step of a solve runs in the HIP
+kernels of libfsp.so; PyTorch supplies device memory and streams.  Importing
+the package does not load the library; the first ``Plan`` does, and it raises
+if ``libfsp.so`` has not been built.
+
+    from paper_2405_02603_amd import Plan
+    plan = Plan(n=256, lo=(-1, -1, -1), hi=(1, 1, 1), greens="vico_dct", prec="f32")
+    phi = plan.solve(rho)          # rho: float32 CUDA tensor of shape (256, 256, 256)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Iterable, List, Optional, Sequence
+
+from . import _lib
+from ._lib import FspError, GREENS, PREC, check
+
+__all__ = ["Plan", "solve_batched", "FspError", "GREENS", "PREC", "library_path", "version"]
+
+_DTYPES = {"f32": "float32", "f64": "float64"}
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def version() -> str:
+    return _lib.load().fsp_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _as3(v, t=float):
+    if isinstance(v, (int, float)):
+        return (t(v),) * 3
+    v = tuple(t(x) for x in v)
+    if len(v) != 3:
+        raise ValueError("expected a scalar or a 3-sequence")
+    return v
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _aligned_bytes(nbytes: int, device, align: int = 256):
+    """A uint8 device tensor of nbytes whose data pointer is align-byte aligned."""
+    torch = _torch()
+    raw = torch.empty(nbytes + align, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % align
+    return raw[off:off + nbytes]
+
+
+class Plan:
+    """One grid size, box, Green's function and precision, with its device buffers.
+
+    ``greens``: "hockney" (Section 2.2), "vico" (Section 2.3, 4N precompute) or
+    "vico_dct" (Section 2.4, (2N+1)^3 DCT-I precompute).
+    ``prec``: "f32" or "f64" (precision of rho, phi and the solve passes; the
+    precompute always runs in float64).
+    """
+
+    def __init__(self, n, lo=(-0.5, -0.5, -0.5), hi=(0.5, 0.5, 0.5), greens: str = "vico_dct",
+                 prec: str = "f32", alpha: float = 1.1, g0: Optional[float] = None, device=None,
+                 precompute: bool = True, stream=None, bind: bool = True):
+        torch = _torch()
+        self._lib = _lib.load()
+        if greens not in GREENS:
+            raise ValueError(f"greens must be one of {sorted(GREENS)}")
+        if prec not in PREC:
+            raise ValueError(f"prec must be one of {sorted(PREC)}")
+        self.n = _as3(n, int)
+        self.lo = _as3(lo)
+        self.hi = _as3(hi)
+        self.greens = greens
+        self.prec = prec
+        self.alpha = float(alpha)
+        self.g0 = g0
+        self.dtype = getattr(torch, _DTYPES[prec])
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        desc = _lib.PlanDesc()
+        desc.n[:] = list(self.n)
+        desc.lo[:] = list(self.lo)
+        desc.hi[:] = list(self.hi)
+        desc.greens = GREENS[greens]
+        desc.prec = PREC[prec]
+        desc.alpha = self.alpha
+        desc.g0 = float("nan") if g0 is None else float(g0)
+        desc.flags = 0
+        h = ctypes.c_void_p()
+        check(self._lib.fsp_plan_create(ctypes.byref(desc), ctypes.byref(h)), "fsp_plan_create")
+        self._h = h
+        gb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        check(self._lib.fsp_plan_bytes(h, ctypes.byref(gb), ctypes.byref(wb)), "fsp_plan_bytes")
+        self.ghat_bytes, self.work_bytes = int(gb.value), int(wb.value)
+        pb = ctypes.c_size_t()
+        check(self._lib.fsp_plan_precompute_bytes(h, ctypes.byref(pb)), "fsp_plan_precompute_bytes")
+        self.precompute_bytes = int(pb.value)
+        off, pitch = ctypes.c_size_t(), ctypes.c_int()
+        check(self._lib.fsp_plan_ghat_layout(h, ctypes.byref(off), ctypes.byref(pitch)), "fsp_plan_ghat_layout")
+        self.octant_offset, self.pitch = int(off.value), int(pitch.value)
+        mb = ctypes.c_double()
+        check(self._lib.fsp_plan_model_bytes(h, ctypes.byref(mb)), "fsp_plan_model_bytes")
+        self.model_bytes = float(mb.value)
+        self.ghat_buf = None
+        self.work_buf = None
+        self._shared_from = None
+        if bind:
+            self.bind()
+            if precompute:
+                self.precompute(stream)
+
+    # ------------------------------------------------------------ buffers
+    def bind(self, ghat=None, work=None) -> None:
+        """Attach device buffers (uint8 tensors, 256-byte aligned); None allocates them with torch."""
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            self.ghat_buf = ghat if ghat is not None else _aligned_bytes(self.ghat_bytes, self.device)
+            self.work_buf = work if work is not None else _aligned_bytes(self.work_bytes, self.device)
+            if self.ghat_buf.numel() < self.ghat_bytes or self.work_buf.numel() < self.work_bytes:
+                raise ValueError("bound buffers are smaller than fsp_plan_bytes")
+            check(self._lib.fsp_plan_bind(self._h, ctypes.c_void_p(self.ghat_buf.data_ptr()),
+                                          ctypes.c_void_p(self.work_buf.data_ptr())), "fsp_plan_bind")
+
+    def precompute(self, stream=None) -> None:
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            check(self._lib.fsp_precompute(self._h, _stream_ptr(stream)), "fsp_precompute")
+
+    def share_ghat(self, src: "Plan") -> None:
+        """Read src's precomputed transform instead of computing one (equal plans only)."""
+        check(self._lib.fsp_plan_share_ghat(self._h, src._h), "fsp_plan_share_ghat")
+        self._shared_from = src  # keep src (and its buffer) alive
+
+    def ghat_octant(self):
+        """View of the stored transform octant [n0+1][n1+1][n2+1] (scaled by V/(8 n0 n1 n2))."""
+        torch = _torch()
+        src = self._shared_from.ghat_octant() if self._shared_from is not None else None
+        if src is not None:
+            return src
+        n0, n1, n2 = self.n
+        esz = 8 if self.prec == "f64" else 4
+        nb = (n0 + 1) * (n1 + 1) * self.pitch * esz
+        raw = self.ghat_buf[self.octant_offset:self.octant_offset + nb]
+        return raw.view(self.dtype).view(n0 + 1, n1 + 1, self.pitch)[:, :, : n2 + 1]
+
+    # ------------------------------------------------------------ solves
+    def _check_field(self, t, name: str) -> None:
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} must be {self.dtype}, got {t.dtype}")
+        if tuple(t.shape) != self.n:
+            raise ValueError(f"{name} must have shape {self.n}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be C-contiguous")
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}")
+
+    def solve(self, rho, out=None, stream=None):
+        """phi for rho (CUDA tensor of the plan's shape and dtype); out may be rho (in place)."""
+        torch = _torch()
+        self._check_field(rho, "rho")
+        if out is None:
+            out = torch.empty_like(rho)
+        self._check_field(out, "out")
+        with torch.cuda.device(self.device):
+            check(self._lib.fsp_solve(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                      _stream_ptr(stream)), "fsp_solve")
+        return out
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fsp_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __repr__(self):
+        return (f"Plan(n={self.n}, lo={self.lo}, hi={self.hi}, greens={self.greens!r}, prec={self.prec!r}, "
+                f"alpha={self.alpha})")
+
+
+def solve_batched(plans: Sequence[Plan], rhos: Sequence, outs: Optional[Sequence] = None, stream=None) -> List:
+    """One call for many independent solves, each with its own plan (and so its own workspace)."""
+    torch = _torch()
+    count = len(plans)
+    if len(rhos) != count:
+        raise ValueError("need one rho per plan")
+    if outs is None:
+        outs = [torch.empty_like(r) for r in rhos]
+    if len(outs) != count:
+        raise ValueError("need one output per plan")
+    for p, r, o in zip(plans, rhos, outs):
+        p._check_field(r, "rho")
+        p._check_field(o, "out")
+    if count == 0:
+        return list(outs)
+    arr = ctypes.c_void_p * count
+    hp = arr(*[p.handle.value for p in plans])
+    rp = arr(*[r.data_ptr() for r in rhos])
+    op = arr(*[o.data_ptr() for o in outs])
+    lib = _lib.load()
+    with torch.cuda.device(plans[0].device):
+        check(lib.fsp_solve_batched(count, hp, rp, op, _stream_ptr(stream)), "fsp_solve_batched")
+    return list(outs)

@@ -1,0 +1,94 @@
+"""ctypes declarations for libfsp.so (the C ABI of include/fsp.h).
+
+Loading fails loudly: there is no fallback implementation of any call.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_size_t, c_uint, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsp.so")
+
+FSP_OK = 0
+FSP_ERR_INVALID_ARG = 1
+FSP_ERR_UNSUPPORTED_SIZE = 2
+FSP_ERR_BOX_ASPECT = 3
+FSP_ERR_OUT_OF_MEMORY = 4
+FSP_ERR_NOT_READY = 5
+FSP_ERR_DEVICE = 6
+
+GREENS = {"hockney": 0, "vico": 1, "vico_dct": 2}
+PREC = {"f32": 0, "f64": 1}
+
+# every symbol include/fsp.h declares
+EXPORTS = (
+    "fsp_plan_create", "fsp_plan_bytes", "fsp_plan_precompute_bytes", "fsp_plan_bind",
+    "fsp_plan_share_ghat", "fsp_precompute", "fsp_solve", "fsp_solve_batched", "fsp_plan_destroy",
+    "fsp_plan_ghat_layout", "fsp_plan_model_bytes", "fsp_status_str", "fsp_last_error", "fsp_version",
+)
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int * 3),
+        ("lo", c_double * 3),
+        ("hi", c_double * 3),
+        ("greens", c_int),
+        ("prec", c_int),
+        ("alpha", c_double),
+        ("g0", c_double),
+        ("flags", c_uint),
+    ]
+
+
+class FspError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfsp.so (built by ``python -m paper_2405_02603_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libfsp.so not found at {path}; build it with "
+                          "`python -m paper_2405_02603_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    P = c_void_p
+    sig = {
+        "fsp_plan_create": (c_int, [POINTER(PlanDesc), POINTER(c_void_p)]),
+        "fsp_plan_bytes": (c_int, [P, POINTER(c_size_t), POINTER(c_size_t)]),
+        "fsp_plan_precompute_bytes": (c_int, [P, POINTER(c_size_t)]),
+        "fsp_plan_bind": (c_int, [P, P, P]),
+        "fsp_plan_share_ghat": (c_int, [P, P]),
+        "fsp_precompute": (c_int, [P, P]),
+        "fsp_solve": (c_int, [P, P, P, P]),
+        "fsp_solve_batched": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), P]),
+        "fsp_plan_destroy": (c_int, [P]),
+        "fsp_plan_ghat_layout": (c_int, [P, POINTER(c_size_t), POINTER(c_int)]),
+        "fsp_plan_model_bytes": (c_int, [P, POINTER(c_double)]),
+        "fsp_status_str": (c_char_p, [c_int]),
+        "fsp_last_error": (c_char_p, []),
+        "fsp_version": (c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(status: int, what: str = "") -> None:
+    if status != FSP_OK:
+        lib = load()
+        name = lib.fsp_status_str(status).decode()
+        detail = lib.fsp_last_error().decode()
+        raise FspError(status, f"{what}: {name}: {detail}" if what else f"{name}: {detail}")

@@ -1,0 +1,536 @@
+// api.hip -- plans, buffers, precompute driver and the C ABI declared in fsp.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fft_core.hpp"
+#include "fsp.h"
+#include "solve_launch.hpp"
+
+namespace fsp {
+hipError_t solve_f32(const SolveGeom& g, const void* rho, void* phi, hipStream_t s);
+hipError_t solve_f64(const SolveGeom& g, const void* rho, void* phi, hipStream_t s);
+hipError_t greens_he_kernel(double* K, const int n[3], const double h[3], double g0, hipStream_t s);
+hipError_t greens_vico_spectrum(double* G, const int samples[3], const double f[3], double L, bool fft_order,
+                                hipStream_t s);
+hipError_t greens_contract(const double* X, double* Y, const double* C, int nout, int nin, long long rest,
+                           hipStream_t s);
+hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int pitch, double scale,
+                               hipStream_t s);
+}  // namespace fsp
+
+namespace {
+
+thread_local std::string g_err;
+
+fsp_status fail(fsp_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+fsp_status fail_hip(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return FSP_ERR_DEVICE;
+}
+
+bool supported_edge(int n) {
+  switch (n) {
+    case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96:
+    case 128: case 192: case 256: case 384: case 512:
+      return true;
+    default:
+      return false;
+  }
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// exp(-2 pi i t / d) in long double, rounded once
+void cis_neg(long long t, long long d, long double* c, long double* s) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  t %= d;
+  const long double a = 2.0L * pi * (long double)t / (long double)d;
+  *c = cosl(a);
+  *s = -sinl(a);
+}
+
+template <typename T>
+void push_c(std::vector<char>& buf, long double re, long double im) {
+  T v[2] = {(T)re, (T)im};
+  const char* p = reinterpret_cast<const char*>(v);
+  buf.insert(buf.end(), p, p + sizeof(v));
+}
+
+// Twiddles of one pencil length: forward order then reversed order (fft_core.hpp layout).
+template <typename T>
+void append_twiddles(std::vector<char>& buf, int L) {
+  for (int rev = 0; rev < 2; ++rev) {
+    const int K = fsp::plan_len(L);
+    for (int s = 1; s < K; ++s) {
+      const int R = fsp::plan_radix(L, rev != 0, s);
+      const int NS = fsp::plan_ns(L, rev != 0, s);
+      for (int k = 0; k < NS; ++k)
+        for (int r = 1; r < R; ++r) {
+          long double c, sn;
+          cis_neg((long long)r * k, (long long)NS * R, &c, &sn);
+          push_c<T>(buf, c, sn);
+        }
+    }
+  }
+}
+
+// DCT-I rows m < nout of a length period+1 transform: C[m][l] = w_l cos(pi l m / period),
+// w_0 = w_period = 1, else 2.
+void dct1_matrix(std::vector<double>& C, int nout, int period) {
+  const int nin = period + 1;
+  const long double pi = 3.141592653589793238462643383279502884L;
+  C.resize((size_t)nout * nin);
+  for (int m = 0; m < nout; ++m)
+    for (int l = 0; l < nin; ++l) {
+      const long long t = ((long long)l * m) % (2LL * period);
+      const long double w = (l == 0 || l == period) ? 1.0L : 2.0L;
+      C[(size_t)m * nin + l] = (double)(w * cosl(pi * (long double)t / (long double)period));
+    }
+}
+
+// Octant rows of the inverse DFT of real, even data on a grid of s = 4n points:
+// C[m][l] = cos(2 pi l m / s), m <= n.
+void dft_cos_matrix(std::vector<double>& C, int nout, int s) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  C.resize((size_t)nout * s);
+  for (int m = 0; m < nout; ++m)
+    for (int l = 0; l < s; ++l) {
+      const long long t = ((long long)l * m) % s;
+      C[(size_t)m * s + l] = (double)cosl(2.0L * pi * (long double)t / (long double)s);
+    }
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  hipError_t enter(int dev) {
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != dev) {
+      e = hipSetDevice(dev);
+      if (e != hipSuccess) return e;
+      changed = true;
+    }
+    return hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct fsp_plan_s {
+  fsp_plan_desc d{};
+  int n[3]{};
+  double h[3]{};
+  double V = 0, L = 0, alpha = 1.1, g0 = 0;
+  int rb = 4;     // bytes per real
+  int pitch = 0;  // complex elements per S row, reals per Green's row
+  size_t tw_row_off = 0, tw_c1_off = 0, tw_c0_off = 0, oct_off = 0;
+  size_t ghat_bytes = 0, work_bytes = 0, pre_bytes = 0;
+  std::vector<char> tw_host;      // image of [0, oct_off) of the Green's buffer
+  std::vector<double> cmat_host;  // cosine matrices used by the precompute
+  void* ghat = nullptr;
+  void* work = nullptr;
+  bool own_ghat = false, own_work = false;
+  const void* ghat_read = nullptr;  // buffer the solves read (own or shared)
+  bool bound = false, ready = false;
+  int device = -1;
+};
+
+namespace {
+
+template <typename T>
+void build_twiddles(fsp_plan_s* p) {
+  std::vector<char>& b = p->tw_host;
+  b.clear();
+  p->tw_row_off = 0;
+  append_twiddles<T>(b, p->n[2]);
+  for (int k = 0; k <= p->n[2]; ++k) {  // split table exp(-i pi k / n2)
+    long double c, s;
+    cis_neg(k, 2LL * p->n[2], &c, &s);
+    push_c<T>(b, c, s);
+  }
+  b.resize(align_up(b.size(), 256), 0);
+  p->tw_c1_off = b.size();
+  append_twiddles<T>(b, 2 * p->n[1]);
+  b.resize(align_up(b.size(), 256), 0);
+  p->tw_c0_off = b.size();
+  append_twiddles<T>(b, 2 * p->n[0]);
+  b.resize(align_up(b.size(), 256), 0);
+  p->oct_off = b.size();
+}
+
+double model_bytes(const fsp_plan_s* p) {
+  // P1 reads rho, writes (n2+1) n1 n0 complex; P2 reads that, writes 2 n1 (n2+1) n0;
+  // P3 reads/writes 2 n1 (n2+1) n0 and reads the octant; P4 mirrors P2, P5 mirrors P1.
+  const double n0 = p->n[0], n1 = p->n[1], n2 = p->n[2], s = p->rb;
+  const double real_grid = n0 * n1 * n2;
+  const double half1 = n0 * n1 * (n2 + 1) * 2;      // reals in (n2+1) n1 n0 complex
+  const double half2 = n0 * 2 * n1 * (n2 + 1) * 2;  // reals in 2 n1 (n2+1) n0 complex
+  const double octant = (n0 + 1) * (n1 + 1) * (n2 + 1);
+  const double reals = 2 * real_grid + 2 * half1 + 2 * (half1 + half2) + 2 * half2 + octant;
+  return reals * s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fsp_status_str(fsp_status s) {
+  switch (s) {
+    case FSP_OK: return "FSP_OK";
+    case FSP_ERR_INVALID_ARG: return "FSP_ERR_INVALID_ARG";
+    case FSP_ERR_UNSUPPORTED_SIZE: return "FSP_ERR_UNSUPPORTED_SIZE";
+    case FSP_ERR_BOX_ASPECT: return "FSP_ERR_BOX_ASPECT";
+    case FSP_ERR_OUT_OF_MEMORY: return "FSP_ERR_OUT_OF_MEMORY";
+    case FSP_ERR_NOT_READY: return "FSP_ERR_NOT_READY";
+    case FSP_ERR_DEVICE: return "FSP_ERR_DEVICE";
+  }
+  return "FSP_ERR_UNKNOWN";
+}
+
+const char* fsp_last_error(void) { return g_err.c_str(); }
+
+const char* fsp_version(void) { return "fsp 0.1.0 gfx950"; }
+
+fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
+  if (!desc || !out) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: NULL argument");
+  *out = nullptr;
+  const fsp_plan_desc& d = *desc;
+  if (d.greens < FSP_HOCKNEY || d.greens > FSP_VICO_DCT)
+    return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: unknown greens value");
+  if (d.prec != FSP_F32 && d.prec != FSP_F64) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: unknown prec value");
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(d.lo[a]) || !std::isfinite(d.hi[a]) || !(d.hi[a] > d.lo[a]))
+      return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: box needs finite lo < hi on every axis");
+    if (!supported_edge(d.n[a]))
+      return fail(FSP_ERR_UNSUPPORTED_SIZE,
+                  "fsp_plan_create: n[" + std::to_string(a) + "] = " + std::to_string(d.n[a]) +
+                      " is not 2^a or 3*2^a in [8, 512]");
+    if (d.greens == FSP_VICO && d.n[a] > 256)
+      return fail(FSP_ERR_UNSUPPORTED_SIZE, "fsp_plan_create: the (4N)^3 Vico-Greengard route is limited to n <= 256");
+  }
+  const double alpha = d.alpha == 0.0 ? 1.1 : d.alpha;
+  if (!std::isfinite(alpha) || !(alpha > 1.0))
+    return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: alpha must exceed 1 (0 selects 1.1)");
+  fsp_plan_s* p = new (std::nothrow) fsp_plan_s();
+  if (!p) return fail(FSP_ERR_OUT_OF_MEMORY, "fsp_plan_create: host allocation failed");
+  p->d = d;
+  p->alpha = alpha;
+  p->g0 = std::isnan(d.g0) ? 1.0 / (4.0 * M_PI) : d.g0;
+  double diag2 = 0, minlen = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    p->n[a] = d.n[a];
+    const double len = d.hi[a] - d.lo[a];
+    p->h[a] = len / d.n[a];
+    diag2 += len * len;
+    minlen = std::min(minlen, len);
+  }
+  p->V = p->h[0] * p->h[1] * p->h[2];
+  p->L = alpha * std::sqrt(diag2);
+  if (d.greens != FSP_HOCKNEY && p->L > 3.0 * minlen) {
+    delete p;
+    return fail(FSP_ERR_BOX_ASPECT,
+                "fsp_plan_create: Vico-Greengard window alpha*|diag| exceeds 3 x the shortest box edge");
+  }
+  p->rb = d.prec == FSP_F64 ? 8 : 4;
+  const int cb = 2 * p->rb;
+  p->pitch = (int)align_up((size_t)p->n[2] + 1, 128 / cb);
+  if (d.prec == FSP_F64)
+    build_twiddles<double>(p);
+  else
+    build_twiddles<float>(p);
+  p->ghat_bytes = align_up(p->oct_off + (size_t)(p->n[0] + 1) * (p->n[1] + 1) * p->pitch * p->rb, 256);
+  p->work_bytes = align_up((size_t)p->n[0] * 2 * p->n[1] * p->pitch * cb, 256);
+  // transient float64 precompute buffers (two ping-pong arrays) + cosine matrices
+  const size_t n0 = p->n[0], n1 = p->n[1], n2 = p->n[2];
+  size_t a = 0, b = 0, cm = 0;
+  if (d.greens == FSP_HOCKNEY) {
+    a = b = (n0 + 1) * (n1 + 1) * (n2 + 1);
+    cm = (n0 + 1) * (n0 + 1) + (n1 + 1) * (n1 + 1) + (n2 + 1) * (n2 + 1);
+  } else if (d.greens == FSP_VICO_DCT) {
+    a = (2 * n0 + 1) * (2 * n1 + 1) * (2 * n2 + 1);
+    b = (2 * n1 + 1) * (2 * n2 + 1) * (n0 + 1);
+    cm = (n0 + 1) * (2 * n0 + 1) + (n1 + 1) * (2 * n1 + 1) + (n2 + 1) * (2 * n2 + 1) + (n0 + 1) * (n0 + 1) +
+         (n1 + 1) * (n1 + 1) + (n2 + 1) * (n2 + 1);
+  } else {
+    a = 64 * n0 * n1 * n2;
+    b = 16 * n1 * n2 * (n0 + 1);
+    cm = (n0 + 1) * 4 * n0 + (n1 + 1) * 4 * n1 + (n2 + 1) * 4 * n2 + (n0 + 1) * (n0 + 1) + (n1 + 1) * (n1 + 1) +
+         (n2 + 1) * (n2 + 1);
+  }
+  p->pre_bytes = align_up(a * 8, 256) + align_up(b * 8, 256) + align_up(cm * 8, 256);
+  *out = p;
+  g_err.clear();
+  return FSP_OK;
+}
+
+fsp_status fsp_plan_bytes(fsp_plan p, size_t* ghat_bytes, size_t* work_bytes) {
+  if (!p) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_bytes: NULL plan");
+  if (ghat_bytes) *ghat_bytes = p->ghat_bytes;
+  if (work_bytes) *work_bytes = p->work_bytes;
+  return FSP_OK;
+}
+
+fsp_status fsp_plan_precompute_bytes(fsp_plan p, size_t* bytes) {
+  if (!p || !bytes) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_precompute_bytes: NULL argument");
+  *bytes = p->pre_bytes;
+  return FSP_OK;
+}
+
+fsp_status fsp_plan_model_bytes(fsp_plan p, double* bytes) {
+  if (!p || !bytes) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_model_bytes: NULL argument");
+  *bytes = model_bytes(p);
+  return FSP_OK;
+}
+
+fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* pitch) {
+  if (!p) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_ghat_layout: NULL plan");
+  if (octant_offset) *octant_offset = p->oct_off;
+  if (pitch) *pitch = p->pitch;
+  return FSP_OK;
+}
+
+static void release_buffers(fsp_plan_s* p) {
+  if (p->own_ghat && p->ghat) (void)hipFree(p->ghat);
+  if (p->own_work && p->work) (void)hipFree(p->work);
+  p->ghat = p->work = nullptr;
+  p->own_ghat = p->own_work = false;
+  p->ghat_read = nullptr;
+  p->bound = p->ready = false;
+}
+
+fsp_status fsp_plan_bind(fsp_plan p, void* ghat_dev, void* work_dev) {
+  if (!p) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_bind: NULL plan");
+  if ((reinterpret_cast<uintptr_t>(ghat_dev) | reinterpret_cast<uintptr_t>(work_dev)) & 255u)
+    return fail(FSP_ERR_INVALID_ARG, "fsp_plan_bind: buffers must be 256-byte aligned");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "fsp_plan_bind: hipGetDevice");
+  release_buffers(p);
+  p->device = dev;
+  if (ghat_dev) {
+    p->ghat = ghat_dev;
+  } else {
+    e = hipMalloc(&p->ghat, p->ghat_bytes);
+    if (e != hipSuccess) {
+      p->ghat = nullptr;
+      (void)hipGetLastError();
+      return fail(FSP_ERR_OUT_OF_MEMORY, "fsp_plan_bind: hipMalloc of the Green's buffer failed");
+    }
+    p->own_ghat = true;
+  }
+  if (work_dev) {
+    p->work = work_dev;
+  } else {
+    e = hipMalloc(&p->work, p->work_bytes);
+    if (e != hipSuccess) {
+      p->work = nullptr;
+      (void)hipGetLastError();
+      release_buffers(p);
+      return fail(FSP_ERR_OUT_OF_MEMORY, "fsp_plan_bind: hipMalloc of the workspace failed");
+    }
+    p->own_work = true;
+  }
+  p->ghat_read = p->ghat;
+  p->bound = true;
+  return FSP_OK;
+}
+
+fsp_status fsp_plan_share_ghat(fsp_plan dst, fsp_plan src) {
+  if (!dst || !src) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_share_ghat: NULL plan");
+  const fsp_plan_desc &a = dst->d, &b = src->d;
+  bool same = a.greens == b.greens && a.prec == b.prec && dst->alpha == src->alpha && dst->g0 == src->g0;
+  for (int i = 0; i < 3; ++i) same = same && a.n[i] == b.n[i] && a.lo[i] == b.lo[i] && a.hi[i] == b.hi[i];
+  if (!same) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_share_ghat: plans differ in kernel, grid, box or precision");
+  if (!src->ready) return fail(FSP_ERR_NOT_READY, "fsp_plan_share_ghat: source plan has no precomputed transform");
+  if (!dst->bound) return fail(FSP_ERR_NOT_READY, "fsp_plan_share_ghat: bind the destination plan first");
+  if (src->device != dst->device) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_share_ghat: plans on different devices");
+  dst->ghat_read = src->ghat_read;
+  dst->ready = true;
+  return FSP_OK;
+}
+
+fsp_status fsp_precompute(fsp_plan p, void* stream) {
+  if (!p) return fail(FSP_ERR_INVALID_ARG, "fsp_precompute: NULL plan");
+  if (!p->bound) return fail(FSP_ERR_NOT_READY, "fsp_precompute: bind buffers first");
+  DeviceGuard guard;
+  hipError_t e = guard.enter(p->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_precompute: hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int* n = p->n;
+  const int gk = p->d.greens;
+  // cosine matrices, in the order they are used
+  std::vector<double>& cm = p->cmat_host;
+  cm.clear();
+  std::vector<size_t> moff;
+  std::vector<double> tmp;
+  auto add = [&](const std::vector<double>& m) {
+    moff.push_back(cm.size());
+    cm.insert(cm.end(), m.begin(), m.end());
+  };
+  if (gk == FSP_VICO_DCT) {
+    for (int a = 0; a < 3; ++a) {
+      dct1_matrix(tmp, n[a] + 1, 2 * n[a]);
+      add(tmp);
+    }
+  } else if (gk == FSP_VICO) {
+    for (int a = 0; a < 3; ++a) {
+      dft_cos_matrix(tmp, n[a] + 1, 4 * n[a]);
+      add(tmp);
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    dct1_matrix(tmp, n[a] + 1, n[a]);
+    add(tmp);
+  }
+  const size_t n0 = n[0], n1 = n[1], n2 = n[2];
+  size_t a_elems, b_elems;
+  if (gk == FSP_HOCKNEY) {
+    a_elems = b_elems = (n0 + 1) * (n1 + 1) * (n2 + 1);
+  } else if (gk == FSP_VICO_DCT) {
+    a_elems = (2 * n0 + 1) * (2 * n1 + 1) * (2 * n2 + 1);
+    b_elems = (2 * n1 + 1) * (2 * n2 + 1) * (n0 + 1);
+  } else {
+    a_elems = 64 * n0 * n1 * n2;
+    b_elems = 16 * n1 * n2 * (n0 + 1);
+  }
+  double *A = nullptr, *B = nullptr, *C = nullptr;
+  e = hipMallocAsync((void**)&A, a_elems * 8, s);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&B, b_elems * 8, s);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&C, cm.size() * 8, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    if (A) (void)hipFreeAsync(A, s);
+    if (B) (void)hipFreeAsync(B, s);
+    return fail(FSP_ERR_OUT_OF_MEMORY, "fsp_precompute: transient float64 buffers could not be allocated");
+  }
+  p->ready = false;
+  e = hipMemcpyAsync(C, cm.data(), cm.size() * 8, hipMemcpyHostToDevice, s);
+  int mi = 0;
+  // current layout dims, leading axis first
+  long long dims[3];
+  double scale = p->V / (8.0 * n0 * n1 * n2);  // folds V and the 1/M^3 of the inverse transform
+  double* X = A;
+  double* Y = B;
+  auto contract = [&](int nout) {
+    // leading axis dims[0] -> nout, rotate to the back
+    const long long rest = dims[1] * dims[2];
+    if (e == hipSuccess)
+      e = fsp::greens_contract(X, Y, C + moff[mi], nout, (int)dims[0], rest, s);
+    ++mi;
+    const long long d0 = dims[0];
+    (void)d0;
+    dims[0] = dims[1];
+    dims[1] = dims[2];
+    dims[2] = nout;
+    std::swap(X, Y);
+  };
+  if (gk == FSP_HOCKNEY) {
+    if (e == hipSuccess) e = fsp::greens_he_kernel(X, n, p->h, p->g0, s);
+    dims[0] = n0 + 1; dims[1] = n1 + 1; dims[2] = n2 + 1;
+  } else {
+    const bool full = gk == FSP_VICO;
+    int samples[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+      samples[a] = full ? 4 * n[a] : 2 * n[a] + 1;
+      f[a] = M_PI / (2.0 * n[a] * p->h[a]);  // k = 2 pi l / (4 n h)
+    }
+    if (e == hipSuccess) e = fsp::greens_vico_spectrum(X, samples, f, p->L, full, s);
+    dims[0] = samples[0]; dims[1] = samples[1]; dims[2] = samples[2];
+    for (int a = 0; a < 3; ++a) contract(n[a] + 1);
+    // inverse transform on the 4n grid: 1 / prod(4 n_d h_d) = 1 / (64 n0 n1 n2 V)
+    scale /= 64.0 * n0 * n1 * n2 * p->V;
+  }
+  for (int a = 0; a < 3; ++a) contract(n[a] + 1);
+  if (e == hipSuccess)
+    e = fsp::greens_store_octant(X, static_cast<char*>(p->ghat) + p->oct_off, p->d.prec == FSP_F64, n, p->pitch,
+                                 scale, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->ghat, p->tw_host.data(), p->tw_host.size(), hipMemcpyHostToDevice, s);
+  (void)hipFreeAsync(A, s);
+  (void)hipFreeAsync(B, s);
+  (void)hipFreeAsync(C, s);
+  if (e != hipSuccess) return fail_hip(e, "fsp_precompute");
+  p->ghat_read = p->ghat;
+  p->ready = true;
+  return FSP_OK;
+}
+
+static fsp_status solve_one(fsp_plan p, const void* rho, void* phi, hipStream_t s) {
+  fsp::SolveGeom g;
+  g.n0 = p->n[0];
+  g.n1 = p->n[1];
+  g.n2 = p->n[2];
+  g.pitch = p->pitch;
+  const char* gb = static_cast<const char*>(p->ghat_read);
+  g.tw_row = gb + p->tw_row_off;
+  g.tw_c1 = gb + p->tw_c1_off;
+  g.tw_c0 = gb + p->tw_c0_off;
+  g.ghat = gb + p->oct_off;
+  g.work = p->work;
+  hipError_t e = p->d.prec == FSP_F64 ? fsp::solve_f64(g, rho, phi, s) : fsp::solve_f32(g, rho, phi, s);
+  if (e != hipSuccess) return fail_hip(e, "fsp_solve");
+  return FSP_OK;
+}
+
+fsp_status fsp_solve(fsp_plan p, const void* rho, void* phi, void* stream) {
+  if (!p || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, "fsp_solve: NULL argument");
+  if (!p->ready) return fail(FSP_ERR_NOT_READY, "fsp_solve: plan has no bound buffers or no precomputed transform");
+  DeviceGuard guard;
+  hipError_t e = guard.enter(p->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_solve: hipSetDevice");
+  return solve_one(p, rho, phi, reinterpret_cast<hipStream_t>(stream));
+}
+
+fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const* rho, void* const* phi,
+                             void* stream) {
+  if (count < 0) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: negative count");
+  if (count == 0) return FSP_OK;
+  if (!plans || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: NULL argument");
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !rho[i] || !phi[i])
+      return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: NULL entry " + std::to_string(i));
+    if (!plans[i]->ready)
+      return fail(FSP_ERR_NOT_READY, "fsp_solve_batched: plan " + std::to_string(i) + " is not ready");
+    if (plans[i]->device != plans[0]->device)
+      return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: plans on different devices");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i] || plans[j]->work == plans[i]->work)
+        return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: two entries share a workspace");
+  }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plans[0]->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_solve_batched: hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int i = 0; i < count; ++i) {
+    fsp_status st = solve_one(plans[i], rho[i], phi[i], s);
+    if (st != FSP_OK) return st;
+  }
+  return FSP_OK;
+}
+
+fsp_status fsp_plan_destroy(fsp_plan p) {
+  if (!p) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_destroy: NULL plan");
+  if (p->own_ghat || p->own_work) {
+    DeviceGuard guard;
+    (void)guard.enter(p->device);
+    release_buffers(p);
+  }
+  delete p;
+  return FSP_OK;
+}
+
+}  // extern "C"

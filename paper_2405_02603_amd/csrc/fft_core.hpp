@@ -1,0 +1,324 @@
+// fft_core.hpp -- radix plans, twiddle-table layout and register/LDS Stockham
+// stages shared by the solve kernels (gfx950, wave64).
+//
+// A pencil of length L is transformed by a sequence of radix-R stages
+// (Stockham autosort, so the output is in natural order with no bit
+// reversal).  Stage s with radix R and span NS = R_0 * ... * R_{s-1} takes,
+// for each butterfly b in [0, L/R), the inputs at rows b + r L/R, multiplies
+// input r by w^(r k) with k = b mod NS and w = exp(-2 pi i / (NS R)), applies
+// a length-R DFT and writes output m to row (b / NS) NS R + k + m NS.
+//
+// Work split: a tile of TC pencils is handled by TC * NQ threads; thread
+// (c, q) owns pencil c of the tile and butterflies b = q + NQ j.  The first
+// stage reads its inputs straight from global memory and the last stage
+// leaves its outputs in registers, at rows b + m L/R, in the same thread that
+// will store them; only the stages in between exchange data through LDS.
+//
+// Forward transforms use the plan in order; inverse transforms use it reversed
+// (the last radix of the forward plan becomes the first of the inverse), so
+// in a forward -> multiply -> inverse sequence the multiply and the first
+// inverse stage need no data exchange.  The first radix of every plan is even:
+// when only the lower half of the rows is non-zero (zero padding) a forward
+// first stage skips inputs r >= R/2, and when only the lower half of an
+// inverse is kept its last stage skips outputs m >= R/2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fsp {
+
+// ---------------------------------------------------------------- plans
+struct RadixPlan {
+  int n;
+  int r[4];
+};
+
+// Radix sequence for each supported pencil length (2^a or 3 * 2^a, 8..1024).
+__host__ __device__ constexpr RadixPlan radix_plan(int L) {
+  switch (L) {
+    case 8: return {1, {8, 0, 0, 0}};
+    case 12: return {2, {4, 3, 0, 0}};
+    case 16: return {1, {16, 0, 0, 0}};
+    case 24: return {2, {8, 3, 0, 0}};
+    case 32: return {2, {8, 4, 0, 0}};
+    case 48: return {2, {16, 3, 0, 0}};
+    case 64: return {2, {8, 8, 0, 0}};
+    case 96: return {3, {8, 4, 3, 0}};
+    case 128: return {2, {16, 8, 0, 0}};
+    case 192: return {3, {8, 8, 3, 0}};
+    case 256: return {2, {16, 16, 0, 0}};
+    case 384: return {3, {16, 8, 3, 0}};
+    case 512: return {3, {8, 8, 8, 0}};
+    case 768: return {3, {16, 16, 3, 0}};
+    case 1024: return {3, {16, 8, 8, 0}};
+    default: return {0, {0, 0, 0, 0}};
+  }
+}
+
+__host__ __device__ constexpr int plan_len(int L) { return radix_plan(L).n; }
+
+// Radix of stage s; REV selects the reversed plan used by inverse transforms.
+__host__ __device__ constexpr int plan_radix(int L, bool rev, int s) {
+  return rev ? radix_plan(L).r[radix_plan(L).n - 1 - s] : radix_plan(L).r[s];
+}
+
+__host__ __device__ constexpr int plan_ns(int L, bool rev, int s) {
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= plan_radix(L, rev, i);
+  return ns;
+}
+
+// Twiddle table of one plan order: stage s >= 1 holds NS * (R - 1) complex
+// values, entry k (R - 1) + (r - 1) = exp(-2 pi i r k / (NS R)).
+__host__ __device__ constexpr int tw_stage_off(int L, bool rev, int s) {
+  int off = 0;
+  for (int i = 1; i < s; ++i) off += plan_ns(L, rev, i) * (plan_radix(L, rev, i) - 1);
+  return off;
+}
+
+__host__ __device__ constexpr int tw_order_size(int L, bool rev) {
+  return tw_stage_off(L, rev, plan_len(L));
+}
+
+// Table for a length: forward order, then reversed order.
+__host__ __device__ constexpr int tw_size(int L) { return tw_order_size(L, false) + tw_order_size(L, true); }
+__host__ __device__ constexpr int tw_base(int L, bool rev) { return rev ? tw_order_size(L, false) : 0; }
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> conjg(cx<T> a) { return {a.x, -a.y}; }
+
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> mul_mi(cx<T> a) {
+  return INV ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
+
+// multiply by the constant (c, s) for the forward transform, (c, -s) for the inverse
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> mul_const(cx<T> a, T c, T s) {
+  const T si = INV ? -s : s;
+  return {a.x * c - a.y * si, a.x * si + a.y * c};
+}
+
+// ---------------------------------------------------------------- butterflies
+// v[m] <- sum_r v[r] exp(-+ 2 pi i r m / R)   (- forward, + inverse)
+template <int R, bool INV, typename T>
+struct Dft;
+
+template <bool INV, typename T>
+struct Dft<2, INV, T> {
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    const cx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV, typename T>
+struct Dft<3, INV, T> {
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    const T h = T(0.86602540378443864676);  // sqrt(3)/2
+    const cx<T> s = cadd(v[1], v[2]);
+    const cx<T> d = mul_mi<INV>(csub(v[1], v[2]));
+    const cx<T> m = {v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y};
+    v[0] = cadd(v[0], s);
+    v[1] = {m.x + h * d.x, m.y + h * d.y};
+    v[2] = {m.x - h * d.x, m.y - h * d.y};
+  }
+};
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  const cx<T> t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  const cx<T> t2 = cadd(a1, a3), t3 = mul_mi<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <bool INV, typename T>
+struct Dft<4, INV, T> {
+  static __device__ __forceinline__ void run(cx<T>* v) { dft4<INV>(v[0], v[1], v[2], v[3]); }
+};
+
+template <bool INV, typename T>
+__device__ __forceinline__ void dft8(cx<T>* v, int st) {
+  // v[0], v[st], ..., v[7 st]
+  cx<T> e0 = v[0], e1 = v[2 * st], e2 = v[4 * st], e3 = v[6 * st];
+  cx<T> o0 = v[st], o1 = v[3 * st], o2 = v[5 * st], o3 = v[7 * st];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  const T r = T(0.70710678118654752440);  // sqrt(1/2)
+  o1 = mul_const<INV>(o1, r, -r);
+  o2 = mul_mi<INV>(o2);
+  o3 = mul_const<INV>(o3, -r, -r);
+  v[0] = cadd(e0, o0);
+  v[4 * st] = csub(e0, o0);
+  v[st] = cadd(e1, o1);
+  v[5 * st] = csub(e1, o1);
+  v[2 * st] = cadd(e2, o2);
+  v[6 * st] = csub(e2, o2);
+  v[3 * st] = cadd(e3, o3);
+  v[7 * st] = csub(e3, o3);
+}
+
+template <bool INV, typename T>
+struct Dft<8, INV, T> {
+  static __device__ __forceinline__ void run(cx<T>* v) { dft8<INV>(v, 1); }
+};
+
+template <bool INV, typename T>
+struct Dft<16, INV, T> {
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    // 16 = 2 x 8: length-8 DFTs of the even and odd samples, then one radix-2 layer.
+    cx<T> e[8], o[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      e[i] = v[2 * i];
+      o[i] = v[2 * i + 1];
+    }
+    dft8<INV>(e, 1);
+    dft8<INV>(o, 1);
+    const T c1 = T(0.92387953251128675613);  // cos(pi/8)
+    const T s1 = T(0.38268343236508977173);  // sin(pi/8)
+    const T r = T(0.70710678118654752440);
+    // o[k] *= exp(-+ 2 pi i k / 16)
+    o[1] = mul_const<INV>(o[1], c1, -s1);
+    o[2] = mul_const<INV>(o[2], r, -r);
+    o[3] = mul_const<INV>(o[3], s1, -c1);
+    o[4] = mul_mi<INV>(o[4]);
+    o[5] = mul_const<INV>(o[5], -s1, -c1);
+    o[6] = mul_const<INV>(o[6], -r, -r);
+    o[7] = mul_const<INV>(o[7], -c1, -s1);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      v[k] = cadd(e[k], o[k]);
+      v[k + 8] = csub(e[k], o[k]);
+    }
+  }
+};
+
+// ---------------------------------------------------------------- stages
+template <typename T, int R, int NS, bool INV>
+__device__ __forceinline__ void apply_twiddles(cx<T>* v, const cx<T>* __restrict__ tw, int k) {
+  if constexpr (NS > 1) {
+    const cx<T>* w = tw + k * (R - 1);
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r - 1]) : cmul(v[r], w[r - 1]);
+  }
+}
+
+// One middle stage: inputs from LDS, outputs back to LDS (in place, two barriers).
+// idx(row) maps a pencil row to this thread's LDS slot.
+template <typename T, int L, bool REV, int S, int NQ, bool INV, class IDX>
+__device__ __forceinline__ void lds_stage(cx<T>* lds, const cx<T>* __restrict__ tw, int q, IDX idx) {
+  constexpr int R = plan_radix(L, REV, S);
+  constexpr int NS = plan_ns(L, REV, S);
+  constexpr int NB = L / R;
+  constexpr int J = (NB + NQ - 1) / NQ;
+  const cx<T>* tws = tw + tw_base(L, REV) + tw_stage_off(L, REV, S);
+  cx<T> v[J][R];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int b = q + NQ * j;
+    if ((NB % NQ == 0) || b < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[j][r] = lds[idx(b + r * NB)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int b = q + NQ * j;
+    if ((NB % NQ == 0) || b < NB) {
+      apply_twiddles<T, R, NS, INV>(v[j], tws, b % NS);
+      Dft<R, INV, T>::run(v[j]);
+      const int base = (b / NS) * NS * R + (b % NS);
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[idx(base + m * NS)] = v[j][m];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int L, bool REV, int S, int SEND, int NQ, bool INV, class IDX>
+__device__ __forceinline__ void lds_stages(cx<T>* lds, const cx<T>* __restrict__ tw, int q, IDX idx) {
+  if constexpr (S < SEND) {
+    lds_stage<T, L, REV, S, NQ, INV>(lds, tw, q, idx);
+    lds_stages<T, L, REV, S + 1, SEND, NQ, INV>(lds, tw, q, idx);
+  }
+}
+
+// Last stage: inputs from LDS, outputs left in registers v[j][m] = row b + m L/R.
+template <typename T, int L, bool REV, int NQ, bool INV, int J, int R, class IDX>
+__device__ __forceinline__ void lds_last_stage(const cx<T>* lds, const cx<T>* __restrict__ tw, int q,
+                                               IDX idx, cx<T> (&v)[J][R]) {
+  constexpr int S = plan_len(L) - 1;
+  constexpr int NS = plan_ns(L, REV, S);
+  constexpr int NB = L / R;
+  static_assert(R == plan_radix(L, REV, S), "register array matches the last radix");
+  static_assert(J == (NB + NQ - 1) / NQ, "register array matches the butterfly split");
+  static_assert(NS == NB, "last stage spans the pencil");
+  const cx<T>* tws = tw + tw_base(L, REV) + tw_stage_off(L, REV, S);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int b = q + NQ * j;
+    if ((NB % NQ == 0) || b < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[j][r] = lds[idx(b + r * NB)];
+      apply_twiddles<T, R, NS, INV>(v[j], tws, b);
+      Dft<R, INV, T>::run(v[j]);
+    }
+  }
+}
+
+// Write first-stage outputs (span 1) to LDS: output m of butterfly b is row b R + m.
+template <typename T, int R, int J, int NB, int NQ, class IDX>
+__device__ __forceinline__ void write_first_outputs(cx<T>* lds, const cx<T> (&v)[J][R], int q, IDX idx) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int b = q + NQ * j;
+    if ((NB % NQ == 0) || b < NB) {
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[idx(b * R + m)] = v[j][m];
+    }
+  }
+}
+
+// Shape helpers for register arrays of the first / last stage.
+template <int L, bool REV, int NQ>
+struct FirstStage {
+  static constexpr int R = plan_radix(L, REV, 0);
+  static constexpr int NB = L / R;
+  static constexpr int J = (NB + NQ - 1) / NQ;
+};
+template <int L, bool REV, int NQ>
+struct LastStage {
+  static constexpr int R = plan_radix(L, REV, plan_len(L) - 1);
+  static constexpr int NB = L / R;
+  static constexpr int J = (NB + NQ - 1) / NQ;
+};
+
+}  // namespace fsp

@@ -1,0 +1,170 @@
+// greens.hip -- float64 precompute of the Green's-function transform (gfx950).
+//
+// Every route ends in the same object: the transform of the mirror-extended
+// real-space kernel on the octant k in [0, n] (real and even, so the octant
+// holds all of it), scaled by V / (8 n0 n1 n2) and rounded once to the solve
+// precision.
+//
+//   Hockney-Eastwood (Section 2.2): K[m] = 1/(4 pi |m h|), K[0] = g0, then a
+//     DCT-I of length n_d + 1 on each axis.
+//   Vico-Greengard, modified (Section 2.4): the kernel of eq. (3) sampled at the
+//     (2n+1)^3 non-negative frequencies of the 4n grid, a DCT-I of length
+//     2 n_d + 1 on each axis keeping only outputs m_d <= n_d (that is the
+//     restriction to the doubled grid), then as Hockney-Eastwood.
+//   Vico-Greengard, original (Section 2.3): eq. (3) sampled on the full
+//     (4n)^3 frequency grid, the inverse transform on that grid evaluated at
+//     the octant outputs m_d <= n_d only (a real cosine sum, since the grid
+//     data are real and even), then as Hockney-Eastwood.
+//
+// Each one-axis transform is a dense contraction of the leading axis with a
+// small cosine matrix that also rotates the axes, Y[rest][m] = sum_l C[m][l]
+// X[l][rest]: after three of them the data are back in [m0][m1][m2] order.
+#include <hip/hip_runtime.h>
+
+namespace fsp {
+
+__global__ __launch_bounds__(256) void k_he_kernel(double* K, int n0, int n1, int n2, double h0, double h1,
+                                                   double h2, double g0) {
+  const long long total = (long long)(n0 + 1) * (n1 + 1) * (n2 + 1);
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int m2 = (int)(i % (n2 + 1));
+  const long long t = i / (n2 + 1);
+  const int m1 = (int)(t % (n1 + 1));
+  const int m0 = (int)(t / (n1 + 1));
+  const double x = m0 * h0, y = m1 * h1, z = m2 * h2;
+  const double r = sqrt(x * x + y * y + z * z);
+  K[i] = (i == 0) ? g0 : 1.0 / (4.0 * M_PI * r);
+}
+
+// Samples of eq. (3): 2 sin^2(L|k|/2) / |k|^2, with L^2/2 at k = 0.
+// s_d samples per axis; index l maps to the integer frequency l (dense
+// non-negative grid, signed == false) or to l - s_d for l >= s_d / 2 (FFT
+// order on the 4n grid, signed == true).  k_d = f_d * frequency.
+__global__ __launch_bounds__(256) void k_vico_spectrum(double* G, int s0, int s1, int s2, double f0,
+                                                       double f1, double f2, double L, int fft_order) {
+  const long long total = (long long)s0 * s1 * s2;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int l2 = (int)(i % s2);
+  const long long t = i / s2;
+  int l1 = (int)(t % s1);
+  int l0 = (int)(t / s1);
+  if (fft_order) {
+    if (l0 >= s0 / 2) l0 -= s0;
+    if (l1 >= s1 / 2) l1 -= s1;
+    if (l2 >= s2 / 2) l2 -= s2;
+  }
+  const double kx = l0 * f0, ky = l1 * f1, kz = l2 * f2;
+  const double k = sqrt(kx * kx + ky * ky + kz * kz);
+  double v;
+  if (k > 0.0) {
+    const double s = sin(0.5 * L * k) / k;
+    v = 2.0 * s * s;
+  } else {
+    v = 0.5 * L * L;
+  }
+  G[i] = v;
+}
+
+// Y[r * nout + m] = sum_{l < nin} C[m * nin + l] * X[l * rest + r]
+// 64 x 64 output tile per 256-thread block, 16-deep slices of l through LDS.
+__global__ __launch_bounds__(256) void k_contract_rotate(const double* __restrict__ X, double* __restrict__ Y,
+                                                         const double* __restrict__ C, int nout, int nin,
+                                                         long long rest) {
+  constexpr int BM = 64, BR = 64, BK = 16;
+  __shared__ double sC[BK][BM + 1];
+  __shared__ double sX[BK][BR + 1];
+  const int tid = threadIdx.x;
+  const int tm = tid % 16, tr = tid / 16;
+  const int m0 = blockIdx.y * BM;
+  const long long r0 = (long long)blockIdx.x * BR;
+  double acc[4][4] = {};
+  for (int l0 = 0; l0 < nin; l0 += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      const int mm = e / BK, ll = e % BK;
+      const int m = m0 + mm, l = l0 + ll;
+      sC[ll][mm] = (m < nout && l < nin) ? C[(long long)m * nin + l] : 0.0;
+    }
+    for (int e = tid; e < BK * BR; e += 256) {
+      const int ll = e / BR, rr = e % BR;
+      const int l = l0 + ll;
+      const long long r = r0 + rr;
+      sX[ll][rr] = (l < nin && r < rest) ? X[(long long)l * rest + r] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ll = 0; ll < BK; ++ll) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sC[ll][tm + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sX[ll][tr + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const long long r = r0 + tr + 16 * j;
+    if (r >= rest) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = m0 + tm + 16 * i;
+      if (m < nout) Y[r * nout + m] = acc[i][j];
+    }
+  }
+}
+
+// out[(k0 (n1+1) + k1) * pitch + k2] = scale * G[(k0 (n1+1) + k1) (n2+1) + k2]
+template <typename T>
+__global__ __launch_bounds__(256) void k_store_octant(const double* __restrict__ G, T* __restrict__ out, int n0,
+                                                      int n1, int n2, int pitch, double scale) {
+  const long long total = (long long)(n0 + 1) * (n1 + 1) * (n2 + 1);
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int k2 = (int)(i % (n2 + 1));
+  const long long rowi = i / (n2 + 1);
+  out[rowi * pitch + k2] = (T)(scale * G[i]);
+}
+
+// ------------------------------------------------------------------ host side
+static unsigned grid1(long long n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t greens_he_kernel(double* K, const int n[3], const double h[3], double g0, hipStream_t s) {
+  const long long total = (long long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
+  hipLaunchKernelGGL(k_he_kernel, dim3(grid1(total)), dim3(256), 0, s, K, n[0], n[1], n[2], h[0], h[1], h[2], g0);
+  return hipGetLastError();
+}
+
+hipError_t greens_vico_spectrum(double* G, const int samples[3], const double f[3], double L, bool fft_order,
+                                hipStream_t s) {
+  const long long total = (long long)samples[0] * samples[1] * samples[2];
+  hipLaunchKernelGGL(k_vico_spectrum, dim3(grid1(total)), dim3(256), 0, s, G, samples[0], samples[1], samples[2],
+                     f[0], f[1], f[2], L, fft_order ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t greens_contract(const double* X, double* Y, const double* C, int nout, int nin, long long rest,
+                           hipStream_t s) {
+  const dim3 grid((unsigned)((rest + 63) / 64), (unsigned)((nout + 63) / 64));
+  hipLaunchKernelGGL(k_contract_rotate, grid, dim3(256), 0, s, X, Y, C, nout, nin, rest);
+  return hipGetLastError();
+}
+
+hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int pitch, double scale,
+                               hipStream_t s) {
+  const long long total = (long long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
+  if (f64)
+    hipLaunchKernelGGL(k_store_octant<double>, dim3(grid1(total)), dim3(256), 0, s, G, (double*)out, n[0], n[1],
+                       n[2], pitch, scale);
+  else
+    hipLaunchKernelGGL(k_store_octant<float>, dim3(grid1(total)), dim3(256), 0, s, G, (float*)out, n[0], n[1],
+                       n[2], pitch, scale);
+  return hipGetLastError();
+}
+
+}  // namespace fsp

@@ -1,0 +1,8 @@
+// Single-precision instantiation of the solve passes.
+#include "solve_launch.hpp"
+
+namespace fsp {
+hipError_t solve_f32(const SolveGeom& g, const void* rho, void* phi, hipStream_t s) {
+  return launch_solve<float>(g, rho, phi, s);
+}
+}  // namespace fsp

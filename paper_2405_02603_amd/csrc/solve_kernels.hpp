@@ -1,0 +1,364 @@
+// solve_kernels.hpp -- the five passes of one free-space solve (gfx950).
+//
+// Data layout.  rho and phi are [n0][n1][n2] real arrays.  The spectrum lives
+// in one complex workspace S laid out [n0][2 n1][P] with P >= n2 + 1 a
+// padded row pitch (rows start on 128-byte boundaries):
+//
+//   P1  rows of rho along axis 2: real transform of length 2 n2 of the
+//       zero-padded row (computed as a complex transform of length n2 plus a
+//       split step); writes the n2 + 1 non-negative frequencies to S rows
+//       (i0, i1 < n1).                                   [Section 2.2, steps 1-2, 4]
+//   P2  columns of S along axis 1: forward transform of length 2 n1 whose
+//       upper half of inputs is the zero padding; writes all 2 n1 rows.
+//   P3  columns of S along axis 0: forward transform of length 2 n0 (upper
+//       half zero), multiply by the real, even transform of the mirror-
+//       extended Green's function, inverse transform, keep rows < n0.
+//                                                          [steps 3-5]
+//   P4  columns of S along axis 1: inverse transform of length 2 n1, keep
+//       rows < n1.
+//   P5  rows of S along axis 2: inverse real transform of length 2 n2 from the
+//       n2 + 1 stored frequencies, keep the first n2 samples -> phi. [step 5]
+//
+// Every pass reads and writes HBM once; the zero padding of rho2 and the
+// unused half of phi2 are never stored.  The transforms are unnormalised: the
+// stored Green's octant carries V / (8 n0 n1 n2).
+//
+// Column passes tile TC adjacent columns (contiguous in memory, so every row
+// of a tile is one contiguous segment); row passes put consecutive lanes on
+// consecutive elements of a row.
+#pragma once
+
+#include "fft_core.hpp"
+
+namespace fsp {
+
+struct ColArgs {
+  void* data;                 // S
+  const void* ghat;           // P3: Green's octant [n0+1][n1+1][Pg] (solve precision)
+  const void* tw;             // twiddle table of this pencil length
+  long long row_stride;       // complex elements between consecutive pencil rows
+  long long outer_stride;     // complex elements between consecutive outer indices
+  int ncols;                  // valid columns (n2 + 1)
+  int ntiles;                 // column tiles per outer index
+  int n1;                     // P3: n1 (pairs k1 and 2 n1 - k1 share a Green's row)
+  long long g_row_stride;     // P3: reals between Green's rows k0
+  long long g_k1_stride;      // P3: reals between Green's rows k1
+};
+
+struct RowArgs {
+  const void* in;
+  void* out;
+  const void* tw;             // twiddles of length n2, then exp(-i pi k / n2), k in [0, n2]
+  int nrows;                  // n0 * n1
+  int n1;
+  int pitch;                  // P
+  long long s_i0_stride;      // complex elements between S planes (2 n1 P)
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> czero() { return {T(0), T(0)}; }
+
+// ----------------------------------------------------------------- P2 / P4
+template <typename T, int L, int TC, int NQ, bool INV>
+__global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
+  constexpr int K = plan_len(L);
+  __shared__ cx<T> lds[K > 1 ? L * TC : 1];
+  const int tid = threadIdx.x;
+  const int c = tid % TC, q = tid / TC;
+  const int tile = blockIdx.x % a.ntiles;
+  const long long outer = blockIdx.x / a.ntiles;
+  const int col = tile * TC + c;
+  const bool cok = col < a.ncols;
+  cx<T>* base = reinterpret_cast<cx<T>*>(a.data) + outer * a.outer_stride + col;
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  const long long rs = a.row_stride;
+  auto idx = [c](int row) { return row * TC + c; };
+  constexpr bool REV = INV;
+  using F = FirstStage<L, REV, NQ>;
+  static_assert(INV || F::R % 2 == 0, "forward plans start with an even radix");
+
+  cx<T> v[F::J][F::R];
+#pragma unroll
+  for (int j = 0; j < F::J; ++j) {
+    const int b = q + NQ * j;
+    const bool ok = cok && ((F::NB % NQ == 0) || b < F::NB);
+#pragma unroll
+    for (int r = 0; r < F::R; ++r) {
+      // forward: rows >= L/2 are the zero padding and are never read
+      const bool pad = !INV && r >= F::R / 2;
+      v[j][r] = (ok && !pad) ? base[(long long)(b + r * F::NB) * rs] : czero<T>();
+    }
+    Dft<F::R, INV, T>::run(v[j]);
+  }
+  if constexpr (K == 1) {
+#pragma unroll
+    for (int j = 0; j < F::J; ++j) {
+      const int b = q + NQ * j;
+      if (cok && ((F::NB % NQ == 0) || b < F::NB)) {
+#pragma unroll
+        for (int m = 0; m < F::R; ++m)
+          if (!INV || m < F::R / 2) base[(long long)(b + m * F::NB) * rs] = v[j][m];
+      }
+    }
+  } else {
+    write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+    __syncthreads();
+    lds_stages<T, L, REV, 1, K - 1, NQ, INV>(lds, tw, q, idx);
+    using Ls = LastStage<L, REV, NQ>;
+    static_assert(!INV || Ls::R % 2 == 0, "inverse plans end with an even radix");
+    cx<T> w[Ls::J][Ls::R];
+    lds_last_stage<T, L, REV, NQ, INV>(lds, tw, q, idx, w);
+#pragma unroll
+    for (int j = 0; j < Ls::J; ++j) {
+      const int b = q + NQ * j;
+      if (cok && ((Ls::NB % NQ == 0) || b < Ls::NB)) {
+#pragma unroll
+        for (int m = 0; m < Ls::R; ++m)
+          if (!INV || m < Ls::R / 2) base[(long long)(b + m * Ls::NB) * rs] = w[j][m];
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- P3
+template <typename T, int L, int TC, int NQ>
+__global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
+  constexpr int K = plan_len(L);
+  __shared__ cx<T> lds[K > 1 ? L * TC : 1];
+  const int tid = threadIdx.x;
+  const int c = tid % TC, q = tid / TC;
+  const int tile = blockIdx.x % a.ntiles;
+  const int p = blockIdx.x / a.ntiles;  // k1 in [0, n1]; also handles 2 n1 - k1
+  const int col = tile * TC + c;
+  const bool cok = col < a.ncols;
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  const long long rs = a.row_stride;
+  auto idx = [c](int row) { return row * TC + c; };
+  using F = FirstStage<L, false, NQ>;   // forward, first stage
+  using Lf = LastStage<L, false, NQ>;   // forward, last stage == inverse, first stage
+  static_assert(F::R % 2 == 0, "forward plans start with an even radix");
+
+  // Green's values for the rows this thread holds after the forward transform.
+  const T* g = reinterpret_cast<const T*>(a.ghat) + (long long)p * a.g_k1_stride + col;
+  T gv[Lf::J][Lf::R];
+#pragma unroll
+  for (int j = 0; j < Lf::J; ++j) {
+    const int b = q + NQ * j;
+    const bool ok = cok && ((Lf::NB % NQ == 0) || b < Lf::NB);
+#pragma unroll
+    for (int m = 0; m < Lf::R; ++m) {
+      const int k0 = b + m * Lf::NB;
+      const int kf = k0 <= L / 2 ? k0 : L - k0;
+      gv[j][m] = ok ? g[(long long)kf * a.g_row_stride] : T(0);
+    }
+  }
+
+  const int npass = (p == 0 || p == a.n1) ? 1 : 2;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int k1 = pass == 0 ? p : 2 * a.n1 - p;
+    cx<T>* base = reinterpret_cast<cx<T>*>(a.data) + (long long)k1 * a.outer_stride + col;
+    if (pass) __syncthreads();
+    cx<T> v[F::J][F::R];
+#pragma unroll
+    for (int j = 0; j < F::J; ++j) {
+      const int b = q + NQ * j;
+      const bool ok = cok && ((F::NB % NQ == 0) || b < F::NB);
+#pragma unroll
+      for (int r = 0; r < F::R; ++r)
+        v[j][r] = (ok && r < F::R / 2) ? base[(long long)(b + r * F::NB) * rs] : czero<T>();
+      Dft<F::R, false, T>::run(v[j]);
+    }
+    if constexpr (K == 1) {
+#pragma unroll
+      for (int j = 0; j < F::J; ++j) {
+        const int b = q + NQ * j;
+        if (cok && ((F::NB % NQ == 0) || b < F::NB)) {
+#pragma unroll
+          for (int m = 0; m < F::R; ++m) v[j][m] = cscale(v[j][m], gv[j][m]);
+          Dft<F::R, true, T>::run(v[j]);
+#pragma unroll
+          for (int m = 0; m < F::R / 2; ++m) base[(long long)(b + m * F::NB) * rs] = v[j][m];
+        }
+      }
+    } else {
+      write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+      __syncthreads();
+      lds_stages<T, L, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
+      cx<T> w[Lf::J][Lf::R];
+      lds_last_stage<T, L, false, NQ, false>(lds, tw, q, idx, w);
+      // multiply, then the first inverse stage (span 1) in registers
+#pragma unroll
+      for (int j = 0; j < Lf::J; ++j) {
+#pragma unroll
+        for (int m = 0; m < Lf::R; ++m) w[j][m] = cscale(w[j][m], gv[j][m]);
+        Dft<Lf::R, true, T>::run(w[j]);
+      }
+      __syncthreads();
+      write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, w, q, idx);
+      __syncthreads();
+      lds_stages<T, L, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
+      using Li = LastStage<L, true, NQ>;
+      static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
+      cx<T> u[Li::J][Li::R];
+      lds_last_stage<T, L, true, NQ, true>(lds, tw, q, idx, u);
+#pragma unroll
+      for (int j = 0; j < Li::J; ++j) {
+        const int b = q + NQ * j;
+        if (cok && ((Li::NB % NQ == 0) || b < Li::NB)) {
+#pragma unroll
+          for (int m = 0; m < Li::R / 2; ++m) base[(long long)(b + m * Li::NB) * rs] = u[j][m];
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- P1
+// Row of n2 = LC reals x (zero-padded to 2 LC): z[n] = x[2n] + i x[2n+1]
+// (n < LC/2, zero above), Z = DFT_LC(z), then for k in [0, LC]
+//   X[k] = (Z[k] + conj Z[LC-k]) / 2 - i e^{-i pi k / LC} (Z[k] - conj Z[LC-k]) / 2.
+template <typename T, int LC, int TR, int NQ>
+__global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
+  constexpr int K = plan_len(LC);
+  constexpr int LP = LC + 1;
+  __shared__ cx<T> lds[TR * LP];
+  const int tid = threadIdx.x;
+  const int q = tid % NQ, c = tid / NQ;
+  const int row = blockIdx.x * TR + c;
+  const bool rok = row < a.nrows;
+  const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in) + (long long)row * (LC / 2);
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  auto idx = [c](int e) { return c * LP + e; };
+  using F = FirstStage<LC, false, NQ>;
+  static_assert(F::R % 2 == 0, "forward plans start with an even radix");
+
+  cx<T> v[F::J][F::R];
+#pragma unroll
+  for (int j = 0; j < F::J; ++j) {
+    const int b = q + NQ * j;
+    const bool ok = rok && ((F::NB % NQ == 0) || b < F::NB);
+#pragma unroll
+    for (int r = 0; r < F::R; ++r) v[j][r] = (ok && r < F::R / 2) ? in[b + r * F::NB] : czero<T>();
+    Dft<F::R, false, T>::run(v[j]);
+  }
+  if constexpr (K == 1) {
+    write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+  } else {
+    write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+    __syncthreads();
+    lds_stages<T, LC, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
+    using Ls = LastStage<LC, false, NQ>;
+    cx<T> w[Ls::J][Ls::R];
+    lds_last_stage<T, LC, false, NQ, false>(lds, tw, q, idx, w);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < Ls::J; ++j) {
+      const int b = q + NQ * j;
+      if ((Ls::NB % NQ == 0) || b < Ls::NB) {
+#pragma unroll
+        for (int m = 0; m < Ls::R; ++m) lds[idx(b + m * Ls::NB)] = w[j][m];
+      }
+    }
+  }
+  __syncthreads();
+  if (!rok) return;
+  const cx<T>* pp = tw + tw_size(LC);
+  const int i0 = row / a.n1, i1 = row - i0 * a.n1;
+  cx<T>* out = reinterpret_cast<cx<T>*>(a.out) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
+  constexpr int JO = (LC + 1 + NQ - 1) / NQ;
+#pragma unroll
+  for (int j = 0; j < JO; ++j) {
+    const int k = q + NQ * j;
+    if (k <= LC) {
+      const cx<T> A = lds[idx(k == LC ? 0 : k)];
+      const cx<T> B = conjg(lds[idx(k == 0 ? 0 : LC - k)]);
+      const cx<T> E = {T(0.5) * (A.x + B.x), T(0.5) * (A.y + B.y)};
+      const cx<T> D = {T(0.5) * (A.x - B.x), T(0.5) * (A.y - B.y)};
+      const cx<T> U = cmul(pp[k], D);
+      out[k] = {E.x + U.y, E.y - U.x};
+    }
+  }
+}
+
+// ----------------------------------------------------------------- P5
+// From X[k], k in [0, LC] (half spectrum of a real row of length 2 LC):
+//   Y[n] = (X[n] + conj X[LC-n]) + i e^{+i pi n / LC} (X[n] - conj X[LC-n]),
+//   z = inverse DFT_LC(Y), x[2n] = Re z[n], x[2n+1] = Im z[n]; keep n < LC/2.
+template <typename T, int LC, int TR, int NQ>
+__global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
+  constexpr int K = plan_len(LC);
+  constexpr int LP = LC + 1;
+  __shared__ cx<T> lds[TR * LP];
+  const int tid = threadIdx.x;
+  const int q = tid % NQ, c = tid / NQ;
+  const int row = blockIdx.x * TR + c;
+  const bool rok = row < a.nrows;
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  auto idx = [c](int e) { return c * LP + e; };
+  {
+    const int i0 = row / a.n1, i1 = row - i0 * a.n1;
+    const cx<T>* in =
+        reinterpret_cast<const cx<T>*>(a.in) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
+    constexpr int JI = (LC + 1 + NQ - 1) / NQ;
+#pragma unroll
+    for (int j = 0; j < JI; ++j) {
+      const int k = q + NQ * j;
+      if (k <= LC) lds[idx(k)] = rok ? in[k] : czero<T>();
+    }
+  }
+  __syncthreads();
+  const cx<T>* pp = tw + tw_size(LC);
+  using F = FirstStage<LC, true, NQ>;
+  cx<T> v[F::J][F::R];
+#pragma unroll
+  for (int j = 0; j < F::J; ++j) {
+    const int b = q + NQ * j;
+    if ((F::NB % NQ == 0) || b < F::NB) {
+#pragma unroll
+      for (int r = 0; r < F::R; ++r) {
+        const int n = b + r * F::NB;
+        const cx<T> X1 = lds[idx(n)];
+        const cx<T> X2 = conjg(lds[idx(LC - n)]);
+        const cx<T> A = cadd(X1, X2);
+        const cx<T> B = cmulc(csub(X1, X2), pp[n]);
+        v[j][r] = {A.x - B.y, A.y + B.x};
+      }
+      Dft<F::R, true, T>::run(v[j]);
+    }
+  }
+  cx<T>* out = reinterpret_cast<cx<T>*>(a.out) + (long long)row * (LC / 2);
+  if constexpr (K == 1) {
+    static_assert(F::R % 2 == 0, "inverse plans end with an even radix");
+    if (rok) {
+#pragma unroll
+      for (int j = 0; j < F::J; ++j) {
+        const int b = q + NQ * j;
+        if ((F::NB % NQ == 0) || b < F::NB) {
+#pragma unroll
+          for (int m = 0; m < F::R / 2; ++m) out[b + m * F::NB] = v[j][m];
+        }
+      }
+    }
+  } else {
+    __syncthreads();
+    write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+    __syncthreads();
+    lds_stages<T, LC, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
+    using Li = LastStage<LC, true, NQ>;
+    static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
+    cx<T> u[Li::J][Li::R];
+    lds_last_stage<T, LC, true, NQ, true>(lds, tw, q, idx, u);
+    if (rok) {
+#pragma unroll
+      for (int j = 0; j < Li::J; ++j) {
+        const int b = q + NQ * j;
+        if ((Li::NB % NQ == 0) || b < Li::NB) {
+#pragma unroll
+          for (int m = 0; m < Li::R / 2; ++m) out[b + m * Li::NB] = u[j][m];
+        }
+      }
+    }
+  }
+}
+
+}  // namespace fsp

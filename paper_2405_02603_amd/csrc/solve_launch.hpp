@@ -1,0 +1,190 @@
+// solve_launch.hpp -- tile shapes per pencil length and the host-side launchers
+// of the five solve passes.  Included by one translation unit per precision.
+#pragma once
+
+#include "solve_kernels.hpp"
+
+namespace fsp {
+
+struct TileCfg {
+  int tiles;  // TC (column passes: columns per block) or TR (row passes: rows per block)
+  int nq;     // threads per pencil
+};
+
+// Column passes (pencil length L = 2 n, strided rows).  LDS = L * TC * sizeof(cx<T>).
+template <typename T>
+__host__ __device__ constexpr TileCfg col_cfg(int L) {
+  constexpr bool d = sizeof(T) == 8;
+  switch (L) {
+    case 16: return {d ? 32 : 64, 1};
+    case 24: return {d ? 32 : 64, 1};
+    case 32: return {32, 4};
+    case 48: return {d ? 32 : 64, 1};
+    case 64: return {d ? 16 : 32, 8};
+    case 96: return {d ? 16 : 32, 4};
+    case 128: return {d ? 16 : 32, 8};
+    case 192: return {d ? 8 : 16, 8};
+    case 256: return {d ? 8 : 16, 16};
+    case 384: return {d ? 8 : 16, 8};
+    case 512: return {d ? 8 : 16, 16};
+    case 768: return {d ? 4 : 8, 16};
+    case 1024: return {d ? 4 : 8, 32};
+    default: return {0, 0};
+  }
+}
+
+// Row passes (pencil length LC = n2 complex, contiguous rows).  LDS = TR (LC + 1) sizeof(cx<T>).
+template <typename T>
+__host__ __device__ constexpr TileCfg row_cfg(int LC) {
+  constexpr bool d = sizeof(T) == 8;
+  switch (LC) {
+    case 8: return {64, 1};
+    case 12: return {64, 1};
+    case 16: return {64, 1};
+    case 24: return {64, 1};
+    case 32: return {32, 4};
+    case 48: return {d ? 32 : 64, 1};
+    case 64: return {32, 8};
+    case 96: return {32, 4};
+    case 128: return {d ? 8 : 16, 8};
+    case 192: return {d ? 8 : 16, 8};
+    case 256: return {d ? 8 : 16, 16};
+    case 384: return {d ? 4 : 8, 8};
+    case 512: return {d ? 4 : 8, 16};
+    default: return {0, 0};
+  }
+}
+
+#define FSP_ROW_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#define FSP_COL_LENGTHS(X) \
+  X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+
+template <typename T>
+hipError_t launch_p1(int LC, const RowArgs& a, hipStream_t s) {
+  switch (LC) {
+#define FSP_CASE(LV)                                                                        \
+  case LV: {                                                                                \
+    constexpr TileCfg c = row_cfg<T>(LV);                                                   \
+    const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                   \
+    hipLaunchKernelGGL((k_row_r2c<T, LV, c.tiles, c.nq>), dim3(blocks), dim3(c.tiles * c.nq), 0, s, a); \
+    break;                                                                                  \
+  }
+    FSP_ROW_LENGTHS(FSP_CASE)
+#undef FSP_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_p5(int LC, const RowArgs& a, hipStream_t s) {
+  switch (LC) {
+#define FSP_CASE(LV)                                                                        \
+  case LV: {                                                                                \
+    constexpr TileCfg c = row_cfg<T>(LV);                                                   \
+    const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                   \
+    hipLaunchKernelGGL((k_row_c2r<T, LV, c.tiles, c.nq>), dim3(blocks), dim3(c.tiles * c.nq), 0, s, a); \
+    break;                                                                                  \
+  }
+    FSP_ROW_LENGTHS(FSP_CASE)
+#undef FSP_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+int col_tiles(int L) {
+  switch (L) {
+#define FSP_CASE(LV) \
+  case LV: return col_cfg<T>(LV).tiles;
+    FSP_COL_LENGTHS(FSP_CASE)
+#undef FSP_CASE
+    default: return 0;
+  }
+}
+
+// nouter: outer pencils groups (P2/P4: n0; P3: n1 + 1 pairs)
+template <typename T>
+hipError_t launch_col(int L, bool inverse, bool conv, const ColArgs& a, int nouter, hipStream_t s) {
+  switch (L) {
+#define FSP_CASE(LV)                                                                              \
+  case LV: {                                                                                      \
+    constexpr TileCfg c = col_cfg<T>(LV);                                                         \
+    const dim3 grid((unsigned)(nouter * a.ntiles));                                               \
+    const dim3 block(c.tiles * c.nq);                                                             \
+    if (conv)                                                                                     \
+      hipLaunchKernelGGL((k_col_conv<T, LV, c.tiles, c.nq>), grid, block, 0, s, a);               \
+    else if (inverse)                                                                             \
+      hipLaunchKernelGGL((k_col_fft<T, LV, c.tiles, c.nq, true>), grid, block, 0, s, a);          \
+    else                                                                                          \
+      hipLaunchKernelGGL((k_col_fft<T, LV, c.tiles, c.nq, false>), grid, block, 0, s, a);         \
+    break;                                                                                        \
+  }
+    FSP_COL_LENGTHS(FSP_CASE)
+#undef FSP_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Geometry of one solve, filled by the plan.
+struct SolveGeom {
+  int n0, n1, n2;
+  int pitch;                 // P
+  const void* tw_row;        // twiddles, length n2 (+ split table)
+  const void* tw_c1;         // twiddles, length 2 n1
+  const void* tw_c0;         // twiddles, length 2 n0
+  const void* ghat;          // octant [n0+1][n1+1][P]
+  void* work;                // S
+};
+
+template <typename T>
+hipError_t launch_solve(const SolveGeom& g, const void* rho, void* phi, hipStream_t s) {
+  const long long P = g.pitch;
+  const long long plane = 2LL * g.n1 * P;  // complex elements per S plane i0
+  RowArgs ra{};
+  ra.nrows = g.n0 * g.n1;
+  ra.n1 = g.n1;
+  ra.pitch = g.pitch;
+  ra.s_i0_stride = plane;
+  ra.tw = g.tw_row;
+  // P1
+  ra.in = rho;
+  ra.out = g.work;
+  hipError_t e = launch_p1<T>(g.n2, ra, s);
+  if (e != hipSuccess) return e;
+  // P2: pencils along axis 1; outer = i0
+  ColArgs ca{};
+  ca.data = g.work;
+  ca.ncols = g.n2 + 1;
+  ca.row_stride = P;
+  ca.outer_stride = plane;
+  ca.tw = g.tw_c1;
+  ca.ntiles = (ca.ncols + col_tiles<T>(2 * g.n1) - 1) / col_tiles<T>(2 * g.n1);
+  e = launch_col<T>(2 * g.n1, false, false, ca, g.n0, s);
+  if (e != hipSuccess) return e;
+  // P3: pencils along axis 0; outer = k1 pairs
+  ColArgs cc{};
+  cc.data = g.work;
+  cc.ghat = g.ghat;
+  cc.ncols = g.n2 + 1;
+  cc.row_stride = plane;
+  cc.outer_stride = P;
+  cc.tw = g.tw_c0;
+  cc.ntiles = (cc.ncols + col_tiles<T>(2 * g.n0) - 1) / col_tiles<T>(2 * g.n0);
+  cc.n1 = g.n1;
+  cc.g_k1_stride = P;
+  cc.g_row_stride = (long long)(g.n1 + 1) * P;
+  e = launch_col<T>(2 * g.n0, false, true, cc, g.n1 + 1, s);
+  if (e != hipSuccess) return e;
+  // P4
+  e = launch_col<T>(2 * g.n1, true, false, ca, g.n0, s);
+  if (e != hipSuccess) return e;
+  // P5
+  ra.in = g.work;
+  ra.out = phi;
+  return launch_p5<T>(g.n2, ra, s);
+}
+
+}  // namespace fsp
