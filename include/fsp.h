@@ -121,6 +121,15 @@ fsp_status fsp_precompute(fsp_plan p, void* stream);
  * allocates nothing.  FSP_ERR_NOT_READY before bind + precompute. */
 fsp_status fsp_solve(fsp_plan p, const void* rho, void* phi, void* stream);
 
+/* The five passes of fsp_solve run one range at a time: passes first..last
+ * (0 = axis-2 real transform of rho, 1 = axis-1 forward, 2 = axis-0 forward,
+ * multiply and inverse, 3 = axis-1 inverse, 4 = axis-2 inverse real transform
+ * to phi).  Running 0..4 in order is fsp_solve; splitting the range lets a
+ * caller put its own events between passes to time each kernel.  rho is read
+ * only by pass 0 and phi written only by pass 4 (the other pointer may be
+ * NULL when its pass is outside the range). */
+fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, int last, void* stream);
+
 /* count independent solves (each with its own plan, and so its own
  * workspace) enqueued on one stream; plans may differ in size, precision and
  * Green's function.  rho[i] / phi[i] as in fsp_solve.  Solves of plans with

@@ -39,10 +39,13 @@ def spacing(n, lo, hi):
 
 
 def apply_axes(a: np.ndarray, mats) -> np.ndarray:
-    """Contract axis d of ``a`` with matrix mats[d] (out_d x in_d), d = 0, 1, 2."""
-    a = np.tensordot(mats[0], a, axes=([1], [0]))            # axis 0
-    a = np.matmul(mats[1], a)                                 # axis 1 (batched over axis 0)
-    a = np.matmul(a, mats[2].T)                               # axis 2
+    """Contract axis d of ``a`` with matrix mats[d] (out_d x in_d), d = 0, 1, 2.
+
+    Each step contracts the leading axis and appends the new axis at the end, so
+    after three steps the axes are back in order (one matrix product per step).
+    """
+    for d in range(3):
+        a = np.tensordot(a, mats[d], axes=([0], [1]))
     return a
 
 

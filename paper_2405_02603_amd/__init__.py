@@ -178,6 +178,16 @@ class Plan:
                                       _stream_ptr(stream)), "fsp_solve")
         return out
 
+    def solve_passes(self, rho, out, first: int, last: int, stream=None):
+        """Run passes first..last (0..4) of a solve; see fsp_solve_passes."""
+        torch = _torch()
+        rp = ctypes.c_void_p(rho.data_ptr() if rho is not None else 0)
+        op = ctypes.c_void_p(out.data_ptr() if out is not None else 0)
+        with torch.cuda.device(self.device):
+            check(self._lib.fsp_solve_passes(self._h, rp, op, int(first), int(last), _stream_ptr(stream)),
+                  "fsp_solve_passes")
+        return out
+
     @property
     def handle(self) -> ctypes.c_void_p:
         return self._h

@@ -3,6 +3,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -13,8 +14,8 @@
 #include "solve_launch.hpp"
 
 namespace fsp {
-hipError_t solve_f32(const SolveGeom& g, const void* rho, void* phi, hipStream_t s);
-hipError_t solve_f64(const SolveGeom& g, const void* rho, void* phi, hipStream_t s);
+hipError_t solve_f32(const SolveGeom& g, const void* rho, void* phi, int first, int last, hipStream_t s);
+hipError_t solve_f64(const SolveGeom& g, const void* rho, void* phi, int first, int last, hipStream_t s);
 hipError_t greens_he_kernel(double* K, const int n[3], const double h[3], double g0, hipStream_t s);
 hipError_t greens_vico_spectrum(double* G, const int samples[3], const double f[3], double L, bool fft_order,
                                 hipStream_t s);
@@ -66,7 +67,8 @@ void push_c(std::vector<char>& buf, long double re, long double im) {
   buf.insert(buf.end(), p, p + sizeof(v));
 }
 
-// Twiddles of one pencil length: forward order then reversed order (fft_core.hpp layout).
+// Twiddles of one pencil length: forward order then reversed order (fft_core.hpp layout):
+// per stage s >= 1 and k in [0, NS): w^(p k) for p = 1, 2, 4, 8, 16, 3, w = exp(-2 pi i / (NS R)).
 template <typename T>
 void append_twiddles(std::vector<char>& buf, int L) {
   for (int rev = 0; rev < 2; ++rev) {
@@ -75,9 +77,9 @@ void append_twiddles(std::vector<char>& buf, int L) {
       const int R = fsp::plan_radix(L, rev != 0, s);
       const int NS = fsp::plan_ns(L, rev != 0, s);
       for (int k = 0; k < NS; ++k)
-        for (int r = 1; r < R; ++r) {
+        for (int e = 0; e < fsp::TW_PER_K; ++e) {
           long double c, sn;
-          cis_neg((long long)r * k, (long long)NS * R, &c, &sn);
+          cis_neg((long long)k * fsp::tw_power(e), (long long)NS * R, &c, &sn);
           push_c<T>(buf, c, sn);
         }
     }
@@ -137,6 +139,8 @@ struct fsp_plan_s {
   double V = 0, L = 0, alpha = 1.1, g0 = 0;
   int rb = 4;     // bytes per real
   int pitch = 0;  // complex elements per S row, reals per Green's row
+  long long plane = 0;  // complex elements between S planes i0
+  int chunks = 1;       // column chunks for passes 1-3
   size_t tw_row_off = 0, tw_c1_off = 0, tw_c0_off = 0, oct_off = 0;
   size_t ghat_bytes = 0, work_bytes = 0, pre_bytes = 0;
   std::vector<char> tw_host;      // image of [0, oct_off) of the Green's buffer
@@ -253,7 +257,13 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
   else
     build_twiddles<float>(p);
   p->ghat_bytes = align_up(p->oct_off + (size_t)(p->n[0] + 1) * (p->n[1] + 1) * p->pitch * p->rb, 256);
-  p->work_bytes = align_up((size_t)p->n[0] * 2 * p->n[1] * p->pitch * cb, 256);
+  {
+    long long pad = 0;
+    if (const char* e = std::getenv("FSP_PLANE_PAD")) pad = std::atoll(e);
+    p->plane = 2LL * p->n[1] * p->pitch + pad;
+    if (const char* e = std::getenv("FSP_CHUNKS")) p->chunks = std::max(1, std::atoi(e));
+  }
+  p->work_bytes = align_up((size_t)p->n[0] * p->plane * cb, 256);
   // transient float64 precompute buffers (two ping-pong arrays) + cosine matrices
   const size_t n0 = p->n[0], n1 = p->n[1], n2 = p->n[2];
   size_t a = 0, b = 0, cm = 0;
@@ -469,19 +479,22 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
   return FSP_OK;
 }
 
-static fsp_status solve_one(fsp_plan p, const void* rho, void* phi, hipStream_t s) {
+static fsp_status solve_one(fsp_plan p, const void* rho, void* phi, hipStream_t s, int first = 0, int last = 4) {
   fsp::SolveGeom g;
   g.n0 = p->n[0];
   g.n1 = p->n[1];
   g.n2 = p->n[2];
   g.pitch = p->pitch;
+  g.plane = p->plane;
+  g.chunks = p->chunks;
   const char* gb = static_cast<const char*>(p->ghat_read);
   g.tw_row = gb + p->tw_row_off;
   g.tw_c1 = gb + p->tw_c1_off;
   g.tw_c0 = gb + p->tw_c0_off;
   g.ghat = gb + p->oct_off;
   g.work = p->work;
-  hipError_t e = p->d.prec == FSP_F64 ? fsp::solve_f64(g, rho, phi, s) : fsp::solve_f32(g, rho, phi, s);
+  hipError_t e = p->d.prec == FSP_F64 ? fsp::solve_f64(g, rho, phi, first, last, s)
+                                      : fsp::solve_f32(g, rho, phi, first, last, s);
   if (e != hipSuccess) return fail_hip(e, "fsp_solve");
   return FSP_OK;
 }
@@ -493,6 +506,17 @@ fsp_status fsp_solve(fsp_plan p, const void* rho, void* phi, void* stream) {
   hipError_t e = guard.enter(p->device);
   if (e != hipSuccess) return fail_hip(e, "fsp_solve: hipSetDevice");
   return solve_one(p, rho, phi, reinterpret_cast<hipStream_t>(stream));
+}
+
+fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, int last, void* stream) {
+  if (!p) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: NULL plan");
+  if (first < 0 || last > 4 || first > last) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: need 0 <= first <= last <= 4");
+  if ((first == 0 && !rho) || (last == 4 && !phi)) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: NULL rho/phi for its pass");
+  if (!p->ready) return fail(FSP_ERR_NOT_READY, "fsp_solve_passes: plan has no bound buffers or no precomputed transform");
+  DeviceGuard guard;
+  hipError_t e = guard.enter(p->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_solve_passes: hipSetDevice");
+  return solve_one(p, rho, phi, reinterpret_cast<hipStream_t>(stream), first, last);
 }
 
 fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const* rho, void* const* phi,

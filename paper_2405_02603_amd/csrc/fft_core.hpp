@@ -48,9 +48,9 @@ __host__ __device__ constexpr RadixPlan radix_plan(int L) {
     case 192: return {3, {8, 8, 3, 0}};
     case 256: return {2, {16, 16, 0, 0}};
     case 384: return {3, {16, 8, 3, 0}};
-    case 512: return {3, {8, 8, 8, 0}};
+    case 512: return {2, {16, 32, 0, 0}};
     case 768: return {3, {16, 16, 3, 0}};
-    case 1024: return {3, {16, 8, 8, 0}};
+    case 1024: return {2, {32, 32, 0, 0}};
     default: return {0, {0, 0, 0, 0}};
   }
 }
@@ -68,11 +68,16 @@ __host__ __device__ constexpr int plan_ns(int L, bool rev, int s) {
   return ns;
 }
 
-// Twiddle table of one plan order: stage s >= 1 holds NS * (R - 1) complex
-// values, entry k (R - 1) + (r - 1) = exp(-2 pi i r k / (NS R)).
+// Twiddle table of one plan order: stage s >= 1 holds, for each k in [0, NS),
+// six complex values w^k, w^2k, w^4k, w^8k, w^16k, w^3k with
+// w = exp(-2 pi i / (NS R)); every other power w^rk (r < 32) is a product of
+// at most three of them.
+constexpr int TW_PER_K = 6;
+__host__ __device__ constexpr int tw_power(int e) { return e == 5 ? 3 : (1 << e); }
+
 __host__ __device__ constexpr int tw_stage_off(int L, bool rev, int s) {
   int off = 0;
-  for (int i = 1; i < s; ++i) off += plan_ns(L, rev, i) * (plan_radix(L, rev, i) - 1);
+  for (int i = 1; i < s; ++i) off += plan_ns(L, rev, i) * TW_PER_K;
   return off;
 }
 
@@ -220,13 +225,96 @@ struct Dft<16, INV, T> {
   }
 };
 
+template <bool INV, typename T>
+struct Dft<32, INV, T> {
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    // 32 = 2 x 16: length-16 DFTs of the even and odd samples, then one radix-2 layer.
+    cx<T> e[16], o[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      e[i] = v[2 * i];
+      o[i] = v[2 * i + 1];
+    }
+    Dft<16, INV, T>::run(e);
+    Dft<16, INV, T>::run(o);
+    const T c1 = T(0.98078528040323044913);  // cos(pi/16)
+    const T s1 = T(0.19509032201612826785);  // sin(pi/16)
+    const T c2 = T(0.92387953251128675613);  // cos(pi/8)
+    const T s2 = T(0.38268343236508977173);  // sin(pi/8)
+    const T c3 = T(0.83146961230254523708);  // cos(3pi/16)
+    const T s3 = T(0.55557023301960222474);  // sin(3pi/16)
+    const T r = T(0.70710678118654752440);
+    // o[k] *= exp(-+ 2 pi i k / 32)
+    o[1] = mul_const<INV>(o[1], c1, -s1);
+    o[2] = mul_const<INV>(o[2], c2, -s2);
+    o[3] = mul_const<INV>(o[3], c3, -s3);
+    o[4] = mul_const<INV>(o[4], r, -r);
+    o[5] = mul_const<INV>(o[5], s3, -c3);
+    o[6] = mul_const<INV>(o[6], s2, -c2);
+    o[7] = mul_const<INV>(o[7], s1, -c1);
+    o[8] = mul_mi<INV>(o[8]);
+    o[9] = mul_const<INV>(o[9], -s1, -c1);
+    o[10] = mul_const<INV>(o[10], -s2, -c2);
+    o[11] = mul_const<INV>(o[11], -s3, -c3);
+    o[12] = mul_const<INV>(o[12], -r, -r);
+    o[13] = mul_const<INV>(o[13], -c3, -s3);
+    o[14] = mul_const<INV>(o[14], -c2, -s2);
+    o[15] = mul_const<INV>(o[15], -c1, -s1);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      v[k] = cadd(e[k], o[k]);
+      v[k + 16] = csub(e[k], o[k]);
+    }
+  }
+};
+
 // ---------------------------------------------------------------- stages
+// Two consecutive complex values of the twiddle table in one load where the type allows.
+template <typename T>
+__device__ __forceinline__ void load_pair(const cx<T>* p, cx<T>& a, cx<T>& b) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 q = *reinterpret_cast<const float4*>(p);
+    a = {q.x, q.y};
+    b = {q.z, q.w};
+  } else {
+    a = p[0];
+    b = p[1];
+  }
+}
+
+// v[r] *= w^(r k) (forward) or its conjugate (inverse), r = 1 .. R-1.
 template <typename T, int R, int NS, bool INV>
 __device__ __forceinline__ void apply_twiddles(cx<T>* v, const cx<T>* __restrict__ tw, int k) {
   if constexpr (NS > 1) {
-    const cx<T>* w = tw + k * (R - 1);
+    const cx<T>* e = tw + k * TW_PER_K;
+    cx<T> w[R];
+    cx<T> w1, w2, w3, w4, w8, w16;
+    load_pair(e, w1, w2);
+    w[1] = w1;
+    if constexpr (R >= 3) w[2] = w2;
+    if constexpr (R >= 4) {
+      load_pair(e + 4, w16, w3);
+      w[3] = w3;
+    }
+    if constexpr (R >= 8) {
+      load_pair(e + 2, w4, w8);
+      w[4] = w4;
+      w[5] = cmul(w4, w1);
+      w[6] = cmul(w4, w2);
+      w[7] = cmul(w4, w3);
+    }
+    if constexpr (R >= 16) {
+      w[8] = w8;
 #pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r - 1]) : cmul(v[r], w[r - 1]);
+      for (int r = 9; r < 16; ++r) w[r] = cmul(w8, w[r - 8]);
+    }
+    if constexpr (R >= 32) {
+      w[16] = w16;
+#pragma unroll
+      for (int r = 17; r < 32; ++r) w[r] = cmul(w16, w[r - 16]);
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
   }
 }
 

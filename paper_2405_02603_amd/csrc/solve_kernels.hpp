@@ -38,7 +38,8 @@ struct ColArgs {
   const void* tw;             // twiddle table of this pencil length
   long long row_stride;       // complex elements between consecutive pencil rows
   long long outer_stride;     // complex elements between consecutive outer indices
-  int ncols;                  // valid columns (n2 + 1)
+  int col0;                   // first column handled by this launch
+  int ncols;                  // end of the valid columns (n2 + 1 or a chunk end)
   int ntiles;                 // column tiles per outer index
   int n1;                     // P3: n1 (pairs k1 and 2 n1 - k1 share a Green's row)
   long long g_row_stride;     // P3: reals between Green's rows k0
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
   const int c = tid % TC, q = tid / TC;
   const int tile = blockIdx.x % a.ntiles;
   const long long outer = blockIdx.x / a.ntiles;
-  const int col = tile * TC + c;
+  const int col = a.col0 + tile * TC + c;
   const bool cok = col < a.ncols;
   cx<T>* base = reinterpret_cast<cx<T>*>(a.data) + outer * a.outer_stride + col;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   const int c = tid % TC, q = tid / TC;
   const int tile = blockIdx.x % a.ntiles;
   const int p = blockIdx.x / a.ntiles;  // k1 in [0, n1]; also handles 2 n1 - k1
-  const int col = tile * TC + c;
+  const int col = a.col0 + tile * TC + c;
   const bool cok = col < a.ncols;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   const long long rs = a.row_stride;

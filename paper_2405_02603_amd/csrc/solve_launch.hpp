@@ -132,6 +132,8 @@ hipError_t launch_col(int L, bool inverse, bool conv, const ColArgs& a, int nout
 struct SolveGeom {
   int n0, n1, n2;
   int pitch;                 // P
+  long long plane;           // complex elements between S planes i0 (>= 2 n1 P)
+  int chunks;                // column chunks for passes 1-3 (1: whole passes)
   const void* tw_row;        // twiddles, length n2 (+ split table)
   const void* tw_c1;         // twiddles, length 2 n1
   const void* tw_c0;         // twiddles, length 2 n0
@@ -139,31 +141,24 @@ struct SolveGeom {
   void* work;                // S
 };
 
+// Passes first..last of one solve (0 = P1 ... 4 = P5).
 template <typename T>
-hipError_t launch_solve(const SolveGeom& g, const void* rho, void* phi, hipStream_t s) {
+hipError_t launch_solve(const SolveGeom& g, const void* rho, void* phi, int first, int last, hipStream_t s) {
   const long long P = g.pitch;
-  const long long plane = 2LL * g.n1 * P;  // complex elements per S plane i0
+  const long long plane = g.plane;  // complex elements per S plane i0
   RowArgs ra{};
   ra.nrows = g.n0 * g.n1;
   ra.n1 = g.n1;
   ra.pitch = g.pitch;
   ra.s_i0_stride = plane;
   ra.tw = g.tw_row;
-  // P1
-  ra.in = rho;
-  ra.out = g.work;
-  hipError_t e = launch_p1<T>(g.n2, ra, s);
-  if (e != hipSuccess) return e;
-  // P2: pencils along axis 1; outer = i0
+  // P2 / P4: pencils along axis 1; outer = i0
   ColArgs ca{};
   ca.data = g.work;
   ca.ncols = g.n2 + 1;
   ca.row_stride = P;
   ca.outer_stride = plane;
   ca.tw = g.tw_c1;
-  ca.ntiles = (ca.ncols + col_tiles<T>(2 * g.n1) - 1) / col_tiles<T>(2 * g.n1);
-  e = launch_col<T>(2 * g.n1, false, false, ca, g.n0, s);
-  if (e != hipSuccess) return e;
   // P3: pencils along axis 0; outer = k1 pairs
   ColArgs cc{};
   cc.data = g.work;
@@ -172,19 +167,48 @@ hipError_t launch_solve(const SolveGeom& g, const void* rho, void* phi, hipStrea
   cc.row_stride = plane;
   cc.outer_stride = P;
   cc.tw = g.tw_c0;
-  cc.ntiles = (cc.ncols + col_tiles<T>(2 * g.n0) - 1) / col_tiles<T>(2 * g.n0);
   cc.n1 = g.n1;
   cc.g_k1_stride = P;
   cc.g_row_stride = (long long)(g.n1 + 1) * P;
-  e = launch_col<T>(2 * g.n0, false, true, cc, g.n1 + 1, s);
-  if (e != hipSuccess) return e;
-  // P4
-  e = launch_col<T>(2 * g.n1, true, false, ca, g.n0, s);
-  if (e != hipSuccess) return e;
-  // P5
-  ra.in = g.work;
-  ra.out = phi;
-  return launch_p5<T>(g.n2, ra, s);
+  const int tc1 = col_tiles<T>(2 * g.n1), tc0 = col_tiles<T>(2 * g.n0);
+  const int ncols = g.n2 + 1;
+  auto set_cols = [&](ColArgs& c, int tcw, int c0, int c1) {
+    c.col0 = c0;
+    c.ncols = c1;
+    c.ntiles = (c1 - c0 + tcw - 1) / tcw;
+  };
+  auto run = [&](int pass, int c0, int c1) -> hipError_t {
+    switch (pass) {
+      case 0:
+        ra.in = rho;
+        ra.out = g.work;
+        return launch_p1<T>(g.n2, ra, s);
+      case 1: set_cols(ca, tc1, c0, c1); return launch_col<T>(2 * g.n1, false, false, ca, g.n0, s);
+      case 2: set_cols(cc, tc0, c0, c1); return launch_col<T>(2 * g.n0, false, true, cc, g.n1 + 1, s);
+      case 3: set_cols(ca, tc1, c0, c1); return launch_col<T>(2 * g.n1, true, false, ca, g.n0, s);
+      case 4:
+        ra.in = g.work;
+        ra.out = phi;
+        return launch_p5<T>(g.n2, ra, s);
+      default: return hipErrorInvalidValue;
+    }
+  };
+  hipError_t e = hipSuccess;
+  if (g.chunks > 1 && first <= 1 && last >= 3) {
+    // passes 1-3 column chunk by column chunk: a chunk's spectrum stays in the
+    // memory-side cache between the three passes
+    if (first == 0) e = run(0, 0, ncols);
+    const int step = tc1 > tc0 ? tc1 : tc0;
+    const int width = ((ncols + g.chunks - 1) / g.chunks + step - 1) / step * step;
+    for (int c0 = 0; c0 < ncols && e == hipSuccess; c0 += width) {
+      const int c1 = c0 + width < ncols ? c0 + width : ncols;
+      for (int pass = 1; pass <= 3 && e == hipSuccess; ++pass) e = run(pass, c0, c1);
+    }
+    if (e == hipSuccess && last == 4) e = run(4, 0, ncols);
+    return e;
+  }
+  for (int pass = first; pass <= last && e == hipSuccess; ++pass) e = run(pass, 0, ncols);
+  return e;
 }
 
 }  // namespace fsp

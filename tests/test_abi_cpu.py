@@ -1,0 +1,135 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared
+symbol, and validates plans on the host (plan creation touches no device)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2405_02603_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "fsp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fsp_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def _desc(n=32, lo=-0.5, hi=0.5, greens=2, prec=0, alpha=1.1, g0=float("nan")):
+    d = _lib.PlanDesc()
+    d.n[:] = list(n) if isinstance(n, tuple) else [n] * 3
+    d.lo[:] = list(lo) if isinstance(lo, tuple) else [lo] * 3
+    d.hi[:] = list(hi) if isinstance(hi, tuple) else [hi] * 3
+    d.greens, d.prec, d.alpha, d.g0, d.flags = greens, prec, alpha, g0, 0
+    return d
+
+
+def _create(lib, d):
+    h = ctypes.c_void_p()
+    st = lib.fsp_plan_create(ctypes.byref(d), ctypes.byref(h))
+    return st, h
+
+
+def test_exports_every_declared_symbol(lib):
+    decl = _declared_symbols()
+    assert len(decl) >= 14
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert sorted(_lib.EXPORTS) == decl
+
+
+def test_version(lib):
+    assert lib.fsp_version().decode().startswith("fsp ")
+
+
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512])
+def test_supported_sizes_create(lib, n):
+    st, h = _create(lib, _desc(n=(n, 8, 12), greens=0))
+    assert st == _lib.FSP_OK
+    assert lib.fsp_plan_destroy(h) == _lib.FSP_OK
+
+
+@pytest.mark.parametrize("n", [0, 4, 7, 10, 20, 40, 100, 640, 768, 1024])
+def test_unsupported_sizes_rejected(lib, n):
+    st, h = _create(lib, _desc(n=(32, n, 32)))
+    assert st == _lib.FSP_ERR_UNSUPPORTED_SIZE
+    assert not h.value
+    assert b"n[1]" in lib.fsp_last_error()
+
+
+def test_invalid_arguments(lib):
+    assert _create(lib, _desc(lo=(0, 0, 0), hi=(1, 0, 1)))[0] == _lib.FSP_ERR_INVALID_ARG
+    assert _create(lib, _desc(hi=float("inf")))[0] == _lib.FSP_ERR_INVALID_ARG
+    assert _create(lib, _desc(greens=3))[0] == _lib.FSP_ERR_INVALID_ARG
+    assert _create(lib, _desc(prec=2))[0] == _lib.FSP_ERR_INVALID_ARG
+    assert _create(lib, _desc(alpha=0.9))[0] == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_plan_create(None, None) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_solve(None, None, None, None) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_plan_destroy(None) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_solve_batched(-1, None, None, None, None) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_solve_batched(0, None, None, None, None) == _lib.FSP_OK
+
+
+def test_box_aspect_limit(lib):
+    # cube: alpha |diag| = 1.1 sqrt(3) L < 3 L
+    assert _create(lib, _desc(greens=2))[0] == _lib.FSP_OK
+    # 2 x 2 x 4 box passes (5.39 <= 6)
+    assert _create(lib, _desc(lo=(-1, -1, -2), hi=(1, 1, 2), greens=2))[0] == _lib.FSP_OK
+    # a thin slab fails for Vico-Greengard but not for Hockney-Eastwood
+    assert _create(lib, _desc(lo=(0, 0, 0), hi=(1, 1, 0.2), greens=2))[0] == _lib.FSP_ERR_BOX_ASPECT
+    assert _create(lib, _desc(lo=(0, 0, 0), hi=(1, 1, 0.2), greens=0))[0] == _lib.FSP_OK
+
+
+def test_original_vico_route_size_limit(lib):
+    assert _create(lib, _desc(n=256, greens=1))[0] == _lib.FSP_OK
+    assert _create(lib, _desc(n=512, greens=1))[0] == _lib.FSP_ERR_UNSUPPORTED_SIZE
+
+
+def test_solve_before_bind_is_not_ready(lib):
+    st, h = _create(lib, _desc())
+    assert st == _lib.FSP_OK
+    dummy = ctypes.c_void_p(256)
+    assert lib.fsp_solve(h, dummy, dummy, None) == _lib.FSP_ERR_NOT_READY
+    assert lib.fsp_precompute(h, None) == _lib.FSP_ERR_NOT_READY
+    assert lib.fsp_solve_passes(h, dummy, dummy, 0, 5, None) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_solve_passes(h, dummy, dummy, 2, 1, None) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_plan_bind(h, ctypes.c_void_p(1), ctypes.c_void_p(256)) == _lib.FSP_ERR_INVALID_ARG
+    lib.fsp_plan_destroy(h)
+
+
+@pytest.mark.parametrize("prec,rb", [(0, 4), (1, 8)])
+@pytest.mark.parametrize("n", [(32, 32, 32), (256, 256, 256), (16, 24, 48)])
+def test_buffer_sizes_and_model_bytes(lib, prec, rb, n):
+    st, h = _create(lib, _desc(n=n, prec=prec))
+    assert st == _lib.FSP_OK
+    g, w = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fsp_plan_bytes(h, ctypes.byref(g), ctypes.byref(w)) == _lib.FSP_OK
+    off, pitch = ctypes.c_size_t(), ctypes.c_int()
+    assert lib.fsp_plan_ghat_layout(h, ctypes.byref(off), ctypes.byref(pitch)) == _lib.FSP_OK
+    n0, n1, n2 = n
+    assert pitch.value >= n2 + 1 and (pitch.value * 2 * rb) % 128 == 0
+    assert off.value % 256 == 0
+    assert g.value >= off.value + (n0 + 1) * (n1 + 1) * pitch.value * rb
+    assert w.value >= n0 * 2 * n1 * pitch.value * 2 * rb
+    mb = ctypes.c_double()
+    assert lib.fsp_plan_model_bytes(h, ctypes.byref(mb)) == _lib.FSP_OK
+    # five passes: 2 N^3 + 24 (N2+1) N0 N1 + (N0+1)(N1+1)(N2+1) reals
+    want = (2 * n0 * n1 * n2 + 24 * (n2 + 1) * n0 * n1 + (n0 + 1) * (n1 + 1) * (n2 + 1)) * rb
+    assert math.isclose(mb.value, want, rel_tol=1e-12)
+    pb = ctypes.c_size_t()
+    assert lib.fsp_plan_precompute_bytes(h, ctypes.byref(pb)) == _lib.FSP_OK
+    assert pb.value > 0
+    lib.fsp_plan_destroy(h)
+
+
+def test_status_strings(lib):
+    for code in range(7):
+        assert lib.fsp_status_str(code).decode().startswith("FSP_")
