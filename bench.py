@@ -56,6 +56,14 @@ def parse(argv=None):
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--skip-f64", action="store_true")
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve"],
+                    help="single: the 256^3 headline; batch: 64 uneven right-hand sides per graph launch; "
+                         "serve: Poisson-arrival serving loop")
+    ap.add_argument("--batch-count", type=int, default=64)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
     return ap.parse_args(argv)
 
 
@@ -131,6 +139,121 @@ def cpu_baseline(rho64, lo, hi, greens_kind, seconds):
                            f"(scipy.fft, workers={cores}), {el:.1f} s; kernel table excluded"}
 
 
+def bench_batch(args):
+    """64 right-hand sides, n from {32,48,64,96,128} (seed 4), Vico-Greengard float32, one graph launch."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2405_02603_amd import Batch, Plan
+
+    items = W.batch_mix(seed=4, count=args.batch_count)
+    src = {}
+    plans, rhos, host = [], [], []
+    for it in items:
+        p = Plan(n=it.n, lo=it.lo, hi=it.hi, greens="vico_dct", prec="f32", precompute=False)
+        if it.n not in src:
+            p.precompute()
+            src[it.n] = p
+        else:
+            p.share_ghat(src[it.n])
+        r = W.source_density(it.n, it.lo, it.hi, it.source)
+        host.append(r)
+        plans.append(p)
+        rhos.append(torch.from_numpy(r).to("cuda", torch.float32))
+    batch = Batch(plans, rhos)
+    for _ in range(args.warmup):
+        batch.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.launch()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    model = sum(p.model_bytes for p in plans)
+    # the same right-hand sides as plain float64 single solves, one at a time
+    p64 = {}
+    r64 = [torch.from_numpy(h).to("cuda") for h in host]
+    for it in items:
+        if it.n not in p64:
+            p64[it.n] = Plan(n=it.n, lo=it.lo, hi=it.hi, greens="vico_dct", prec="f64")
+    outs64 = [p64[it.n].solve(r) for it, r in zip(items, r64)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = max(1, args.steps // 4)
+    for _ in range(reps):
+        for it, r, o in zip(items, r64, outs64):
+            p64[it.n].solve(r, o)
+    torch.cuda.synchronize()
+    ms64 = (time.perf_counter() - t0) * 1e3 / reps
+    err = max(float(torch.linalg.vector_norm((o32.double() - o64).flatten()) / torch.linalg.vector_norm(o64.flatten()))
+              for o32, o64 in zip(batch.outs, outs64))
+    sizes = sorted({it.n for it in items})
+    out = {
+        "metric": "batched Vico-Greengard solves/s (64 uneven right-hand sides per graph launch)",
+        "value": round(len(items) * 1e3 / ms, 1), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(items)} right-hand sides, n in {sizes} (seed 4), [-1,1]^3, 8 Gaussians each, "
+                               "vico_dct float32, one captured graph per step"},
+        "hbm_frac_model": round(model / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "model_bytes_per_step": model,
+        "fp64_single_solves": {"solves_per_s": round(len(items) * 1e3 / ms64, 1), "ms_per_batch": round(ms64, 4)},
+        "max_rel_l2_f32_vs_gpu_f64": err,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serve(args):
+    """Poisson arrivals, n in {32..256}, 50/50 Hockney/Vico, float32, 1% float64 spot checks."""
+    import torch
+
+    import workloads as W
+    from paper_2405_02603_amd.serve import GpuExecutor, Job, Server
+
+    sizes = (32, 48, 64, 96, 128, 192, 256)
+    reqs = W.poisson_arrivals(rate=args.serve_rate, duration=args.serve_seconds, seed=5, sizes=sizes,
+                              spot_fraction=0.01, blobs=8)
+    pool = {}
+    for n in sizes:
+        r = W.source_density(n, (-1.0,) * 3, (1.0,) * 3, W.multiblob(seed=100 + n))
+        for dt in (torch.float32, torch.float64):
+            pool[(n, dt)] = torch.from_numpy(r).to(dt).pin_memory()
+    ex = GpuExecutor(slots=args.serve_slots, source_for=lambda j, dt: pool[(j.n, dt)])
+    ex.warm([(n, g, p) for n in sizes for g in ("hockney", "vico_dct") for p in ("f32", "f64")])
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def run(scale):
+        jobs = [Job(rid=r.rid, t_arrival=r.t_arrival, n=r.n, greens="hockney" if r.greens == "hockney" else "vico_dct",
+                    spot_check=r.spot_check) for r in reqs]
+        srv = Server(ex, budget_bytes=budget, slots=args.serve_slots)
+        return srv.run(jobs, time_scale=scale)
+
+    rep = run(1.0)
+    sweep = []
+    for scale in (0.2, 0.05, 0.01, 0.0):
+        r = run(scale)
+        sweep.append({"offered_rate": (args.serve_rate / scale) if scale else "all-at-once",
+                      "solves_per_s": round(r["solves_per_s"], 1), "p50_ms": round(r["p50_ms"], 3),
+                      "p99_ms": round(r["p99_ms"], 3)})
+    out = {
+        "metric": "served solves/s and p50/p99 latency (Poisson arrivals, mixed sizes and kernels)",
+        "value": round(rep["solves_per_s"], 1), "unit": "solves/s", "n_gpus": 1, "steps": rep["done"],
+        "warmup": 0, "ms_per_step": round(1e3 / max(rep["solves_per_s"], 1e-9), 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Poisson arrivals {args.serve_rate}/s for {args.serve_seconds} s, n in {list(sizes)}, "
+                               "50/50 hockney/vico_dct, float32, 1% float64 spot checks, "
+                               f"budget {args.serve_budget_gb} GB, {args.serve_slots} slots"},
+        "p50_ms": round(rep["p50_ms"], 3), "p99_ms": round(rep["p99_ms"], 3), "requests": rep["requests"],
+        "rejected": rep["rejected"], "launches": rep["launches"], "peak_bytes": rep["peak_bytes"],
+        "spot_checks": rep["spot_checks"], "spot_rel_l2_max": rep["spot_rel_l2_max"],
+        "saturation_sweep": sweep,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     args = parse(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -139,6 +262,10 @@ def main(argv=None):
                                    "part of this build (batched and served solves shard by request)",
                           "n_gpus": args.gpus}))
         return 2
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch

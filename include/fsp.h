@@ -45,6 +45,7 @@ extern "C" {
 #endif
 
 typedef struct fsp_plan_s* fsp_plan;
+typedef struct fsp_batch_s* fsp_batch;
 
 typedef enum {
   FSP_OK = 0,
@@ -137,16 +138,31 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
 fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const* rho,
                              void* const* phi, void* stream);
 
+/* A fixed set of solves replayed as one HIP graph (no per-call launch cost).
+ * fsp_batch_create records count (plan, rho, phi) triples with the rules of
+ * fsp_solve_batched; nothing is enqueued.  The plans, their bound buffers and
+ * the rho/phi arrays must stay alive and unchanged (no re-bind, no
+ * re-precompute into other buffers) while the batch exists.  The first
+ * fsp_batch_launch captures the grouped launches of all solves into a graph
+ * (equal shapes share launches; launch groups become parallel branches) and
+ * launches it on `stream`; later calls replay the same graph.  Concurrent
+ * launches of one batch race on its workspaces. */
+fsp_status fsp_batch_create(int count, const fsp_plan* plans, const void* const* rho, void* const* phi,
+                            fsp_batch* out);
+fsp_status fsp_batch_launch(fsp_batch b, void* stream);
+fsp_status fsp_batch_destroy(fsp_batch b);
+
 /* Free the plan and any buffer it allocated.  Caller-owned buffers are not
  * touched.  Work still queued on a stream must finish first. */
 fsp_status fsp_plan_destroy(fsp_plan p);
 
-/* Where the transform of the Green's function sits in the Green's buffer:
- * *octant_offset is the byte offset of element [0][0][0] of a
- * [n0+1][n1+1][*pitch] array of the solve precision holding the octant
- * k in [0,n] (scaled by V / (8 n0 n1 n2)); elements k2 > n2 of a row are
- * padding.  Either pointer may be NULL. */
-fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* pitch);
+/* Where the transform of the Green's function sits in the Green's buffer.
+ * The octant k in [0,n] (scaled by V / (8 n0 n1 n2), solve precision) is
+ * stored in column tiles of *tile values of k2: element (k0, k1, k2) is at
+ * byte *octant_offset + sizeof(real) * (((k1 * T + k2 / tile) * (n0 + 1) + k0)
+ * * tile + k2 % tile), T = ceil((n2 + 1) / tile); slots with k2 > n2 hold 0.
+ * Either pointer may be NULL. */
+fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* tile);
 
 /* Model bytes that one solve moves through HBM with this plan's schedule
  * (reads + writes of the five passes, the Green's octant included). */

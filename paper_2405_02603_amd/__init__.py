@@ -18,7 +18,7 @@ from typing import Iterable, List, Optional, Sequence
 from . import _lib
 from ._lib import FspError, GREENS, PREC, check
 
-__all__ = ["Plan", "solve_batched", "FspError", "GREENS", "PREC", "library_path", "version"]
+__all__ = ["Plan", "Batch", "solve_batched", "FspError", "GREENS", "PREC", "library_path", "version"]
 
 _DTYPES = {"f32": "float32", "f64": "float64"}
 
@@ -107,9 +107,9 @@ class Plan:
         pb = ctypes.c_size_t()
         check(self._lib.fsp_plan_precompute_bytes(h, ctypes.byref(pb)), "fsp_plan_precompute_bytes")
         self.precompute_bytes = int(pb.value)
-        off, pitch = ctypes.c_size_t(), ctypes.c_int()
-        check(self._lib.fsp_plan_ghat_layout(h, ctypes.byref(off), ctypes.byref(pitch)), "fsp_plan_ghat_layout")
-        self.octant_offset, self.pitch = int(off.value), int(pitch.value)
+        off, tile = ctypes.c_size_t(), ctypes.c_int()
+        check(self._lib.fsp_plan_ghat_layout(h, ctypes.byref(off), ctypes.byref(tile)), "fsp_plan_ghat_layout")
+        self.octant_offset, self.octant_tile = int(off.value), int(tile.value)
         mb = ctypes.c_double()
         check(self._lib.fsp_plan_model_bytes(h, ctypes.byref(mb)), "fsp_plan_model_bytes")
         self.model_bytes = float(mb.value)
@@ -144,16 +144,20 @@ class Plan:
         self._shared_from = src  # keep src (and its buffer) alive
 
     def ghat_octant(self):
-        """View of the stored transform octant [n0+1][n1+1][n2+1] (scaled by V/(8 n0 n1 n2))."""
+        """The stored transform octant as a [n0+1][n1+1][n2+1] tensor (scaled by V/(8 n0 n1 n2))."""
         torch = _torch()
         src = self._shared_from.ghat_octant() if self._shared_from is not None else None
         if src is not None:
             return src
         n0, n1, n2 = self.n
         esz = 8 if self.prec == "f64" else 4
-        nb = (n0 + 1) * (n1 + 1) * self.pitch * esz
-        raw = self.ghat_buf[self.octant_offset:self.octant_offset + nb]
-        return raw.view(self.dtype).view(n0 + 1, n1 + 1, self.pitch)[:, :, : n2 + 1]
+        t = self.octant_tile
+        tiles = (n2 + 1 + t - 1) // t
+        nb = (n1 + 1) * tiles * (n0 + 1) * t * esz
+        raw = self.ghat_buf[self.octant_offset:self.octant_offset + nb].view(self.dtype)
+        blocked = raw.view(n1 + 1, tiles, n0 + 1, t)            # [k1][tile][k0][c]
+        full = blocked.permute(2, 0, 1, 3).reshape(n0 + 1, n1 + 1, tiles * t)
+        return full[:, :, : n2 + 1]
 
     # ------------------------------------------------------------ solves
     def _check_field(self, t, name: str) -> None:
@@ -231,3 +235,49 @@ def solve_batched(plans: Sequence[Plan], rhos: Sequence, outs: Optional[Sequence
     with torch.cuda.device(plans[0].device):
         check(lib.fsp_solve_batched(count, hp, rp, op, _stream_ptr(stream)), "fsp_solve_batched")
     return list(outs)
+
+
+class Batch:
+    """A fixed set of solves replayed as one captured HIP graph (fsp_batch_*).
+
+    The plans, rho and out tensors are held for the batch's lifetime; the first
+    launch captures the graph, later launches replay it.
+    """
+
+    def __init__(self, plans: Sequence[Plan], rhos: Sequence, outs: Optional[Sequence] = None):
+        torch = _torch()
+        count = len(plans)
+        if count == 0 or len(rhos) != count:
+            raise ValueError("need one rho per plan and at least one solve")
+        if outs is None:
+            outs = [torch.empty_like(r) for r in rhos]
+        for p, r, o in zip(plans, rhos, outs):
+            p._check_field(r, "rho")
+            p._check_field(o, "out")
+        self.plans, self.rhos, self.outs = list(plans), list(rhos), list(outs)
+        self.device = self.plans[0].device
+        arr = ctypes.c_void_p * count
+        hp = arr(*[p.handle.value for p in self.plans])
+        rp = arr(*[r.data_ptr() for r in self.rhos])
+        op = arr(*[o.data_ptr() for o in self.outs])
+        self._lib = _lib.load()
+        h = ctypes.c_void_p()
+        check(self._lib.fsp_batch_create(count, hp, rp, op, ctypes.byref(h)), "fsp_batch_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        torch = _torch()
+        with torch.cuda.device(self.device):
+            check(self._lib.fsp_batch_launch(self._h, _stream_ptr(stream)), "fsp_batch_launch")
+        return self.outs
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fsp_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -27,6 +27,7 @@ EXPORTS = (
     "fsp_plan_create", "fsp_plan_bytes", "fsp_plan_precompute_bytes", "fsp_plan_bind",
     "fsp_plan_share_ghat", "fsp_precompute", "fsp_solve", "fsp_solve_passes", "fsp_solve_batched", "fsp_plan_destroy",
     "fsp_plan_ghat_layout", "fsp_plan_model_bytes", "fsp_status_str", "fsp_last_error", "fsp_version",
+    "fsp_batch_create", "fsp_batch_launch", "fsp_batch_destroy",
 )
 
 
@@ -73,6 +74,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "fsp_solve_passes": (c_int, [P, P, P, c_int, c_int, P]),
         "fsp_solve_batched": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), P]),
         "fsp_plan_destroy": (c_int, [P]),
+        "fsp_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                     POINTER(c_void_p)]),
+        "fsp_batch_launch": (c_int, [P, P]),
+        "fsp_batch_destroy": (c_int, [P]),
         "fsp_plan_ghat_layout": (c_int, [P, POINTER(c_size_t), POINTER(c_int)]),
         "fsp_plan_model_bytes": (c_int, [P, POINTER(c_double)]),
         "fsp_status_str": (c_char_p, [c_int]),

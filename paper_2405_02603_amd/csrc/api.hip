@@ -14,15 +14,17 @@
 #include "solve_launch.hpp"
 
 namespace fsp {
-hipError_t solve_f32(const SolveGeom& g, const void* rho, void* phi, int first, int last, hipStream_t s);
-hipError_t solve_f64(const SolveGeom& g, const void* rho, void* phi, int first, int last, hipStream_t s);
+hipError_t solve_f32(const SolveGeom& g, int first, int last, hipStream_t s);
+hipError_t solve_f64(const SolveGeom& g, int first, int last, hipStream_t s);
 hipError_t greens_he_kernel(double* K, const int n[3], const double h[3], double g0, hipStream_t s);
 hipError_t greens_vico_spectrum(double* G, const int samples[3], const double f[3], double L, bool fft_order,
                                 hipStream_t s);
 hipError_t greens_contract(const double* X, double* Y, const double* C, int nout, int nin, long long rest,
                            hipStream_t s);
-hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int pitch, double scale,
+hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int tile, double scale,
                                hipStream_t s);
+int conv_tile_f32(int L);
+int conv_tile_f64(int L);
 }  // namespace fsp
 
 namespace {
@@ -138,7 +140,8 @@ struct fsp_plan_s {
   double h[3]{};
   double V = 0, L = 0, alpha = 1.1, g0 = 0;
   int rb = 4;     // bytes per real
-  int pitch = 0;  // complex elements per S row, reals per Green's row
+  int pitch = 0;  // complex elements per S row
+  int gtile = 0;  // column tile of the blocked Green's octant
   long long plane = 0;  // complex elements between S planes i0
   int chunks = 1;       // column chunks for passes 1-3
   size_t tw_row_off = 0, tw_c1_off = 0, tw_c0_off = 0, oct_off = 0;
@@ -256,7 +259,12 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     build_twiddles<double>(p);
   else
     build_twiddles<float>(p);
-  p->ghat_bytes = align_up(p->oct_off + (size_t)(p->n[0] + 1) * (p->n[1] + 1) * p->pitch * p->rb, 256);
+  p->gtile = d.prec == FSP_F64 ? fsp::conv_tile_f64(2 * p->n[0]) : fsp::conv_tile_f32(2 * p->n[0]);
+  {
+    const size_t tiles = (p->n[2] + 1 + p->gtile - 1) / p->gtile;
+    p->ghat_bytes =
+        align_up(p->oct_off + (size_t)(p->n[1] + 1) * tiles * (p->n[0] + 1) * p->gtile * p->rb, 256);
+  }
   {
     long long pad = 0;
     if (const char* e = std::getenv("FSP_PLANE_PAD")) pad = std::atoll(e);
@@ -264,6 +272,11 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     if (const char* e = std::getenv("FSP_CHUNKS")) p->chunks = std::max(1, std::atoi(e));
   }
   p->work_bytes = align_up((size_t)p->n[0] * p->plane * cb, 256);
+  // the column kernels address a pencil's rows with 32-bit element offsets
+  if ((long long)(2 * p->n[0]) * p->plane >= (1LL << 31)) {
+    delete p;
+    return fail(FSP_ERR_UNSUPPORTED_SIZE, "fsp_plan_create: workspace plane offsets exceed 32 bits");
+  }
   // transient float64 precompute buffers (two ping-pong arrays) + cosine matrices
   const size_t n0 = p->n[0], n1 = p->n[1], n2 = p->n[2];
   size_t a = 0, b = 0, cm = 0;
@@ -306,10 +319,10 @@ fsp_status fsp_plan_model_bytes(fsp_plan p, double* bytes) {
   return FSP_OK;
 }
 
-fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* pitch) {
+fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* tile) {
   if (!p) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_ghat_layout: NULL plan");
   if (octant_offset) *octant_offset = p->oct_off;
-  if (pitch) *pitch = p->pitch;
+  if (tile) *tile = p->gtile;
   return FSP_OK;
 }
 
@@ -467,7 +480,7 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
   }
   for (int a = 0; a < 3; ++a) contract(n[a] + 1);
   if (e == hipSuccess)
-    e = fsp::greens_store_octant(X, static_cast<char*>(p->ghat) + p->oct_off, p->d.prec == FSP_F64, n, p->pitch,
+    e = fsp::greens_store_octant(X, static_cast<char*>(p->ghat) + p->oct_off, p->d.prec == FSP_F64, n, p->gtile,
                                  scale, s);
   if (e == hipSuccess) e = hipMemcpyAsync(p->ghat, p->tw_host.data(), p->tw_host.size(), hipMemcpyHostToDevice, s);
   (void)hipFreeAsync(A, s);
@@ -479,8 +492,10 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
   return FSP_OK;
 }
 
-static fsp_status solve_one(fsp_plan p, const void* rho, void* phi, hipStream_t s, int first = 0, int last = 4) {
-  fsp::SolveGeom g;
+// Shape fields shared by every item of a launch group (items filled by the caller).
+static fsp::SolveGeom group_geom(const fsp_plan_s* p) {
+  fsp::SolveGeom g{};
+  g.items = 0;
   g.n0 = p->n[0];
   g.n1 = p->n[1];
   g.n2 = p->n[2];
@@ -491,11 +506,77 @@ static fsp_status solve_one(fsp_plan p, const void* rho, void* phi, hipStream_t 
   g.tw_row = gb + p->tw_row_off;
   g.tw_c1 = gb + p->tw_c1_off;
   g.tw_c0 = gb + p->tw_c0_off;
-  g.ghat = gb + p->oct_off;
-  g.work = p->work;
-  hipError_t e = p->d.prec == FSP_F64 ? fsp::solve_f64(g, rho, phi, first, last, s)
-                                      : fsp::solve_f32(g, rho, phi, first, last, s);
+  return g;
+}
+
+static void add_item(fsp::SolveGeom& g, const fsp_plan_s* p, const void* rho, void* phi) {
+  const int i = g.items++;
+  g.ghat[i] = static_cast<const char*>(p->ghat_read) + p->oct_off;
+  g.work[i] = p->work;
+  g.rho[i] = rho;
+  g.phi[i] = phi;
+}
+
+static bool same_shape(const fsp_plan_s* a, const fsp_plan_s* b) {
+  return a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] && a->d.prec == b->d.prec &&
+         a->pitch == b->pitch && a->plane == b->plane && a->chunks == b->chunks;
+}
+
+static hipError_t run_group(const fsp::SolveGeom& g, bool f64, int first, int last, hipStream_t s) {
+  return f64 ? fsp::solve_f64(g, first, last, s) : fsp::solve_f32(g, first, last, s);
+}
+
+static fsp_status solve_one(fsp_plan p, const void* rho, void* phi, hipStream_t s, int first = 0, int last = 4) {
+  fsp::SolveGeom g = group_geom(p);
+  add_item(g, p, rho, phi);
+  hipError_t e = run_group(g, p->d.prec == FSP_F64, first, last, s);
   if (e != hipSuccess) return fail_hip(e, "fsp_solve");
+  return FSP_OK;
+}
+
+// Items of equal shape share launches (up to MAX_ITEMS per launch); launch
+// group k goes to streams[k % nstreams].
+static fsp_status enqueue_batch(int count, const fsp_plan* plans, const void* const* rho, void* const* phi,
+                                const hipStream_t* streams, int nstreams) {
+  std::vector<char> done(count, 0);
+  int group = 0;
+  for (int i = 0; i < count; ++i) {
+    if (done[i]) continue;
+    fsp::SolveGeom g = group_geom(plans[i]);
+    for (int j = i; j < count; ++j) {
+      if (done[j] || !same_shape(plans[i], plans[j])) continue;
+      add_item(g, plans[j], rho[j], phi[j]);
+      done[j] = 1;
+      if (g.items == fsp::MAX_ITEMS) {
+        hipError_t e = run_group(g, plans[i]->d.prec == FSP_F64, 0, 4, streams[group++ % nstreams]);
+        if (e != hipSuccess) return fail_hip(e, "fsp_solve_batched");
+        g = group_geom(plans[i]);
+      }
+    }
+    if (g.items) {
+      hipError_t e = run_group(g, plans[i]->d.prec == FSP_F64, 0, 4, streams[group++ % nstreams]);
+      if (e != hipSuccess) return fail_hip(e, "fsp_solve_batched");
+    }
+  }
+  return FSP_OK;
+}
+
+static fsp_status check_batch(const char* who, int count, const fsp_plan* plans, const void* const* rho,
+                              void* const* phi) {
+  if (count < 0) return fail(FSP_ERR_INVALID_ARG, std::string(who) + ": negative count");
+  if (count == 0) return FSP_OK;
+  if (!plans || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, std::string(who) + ": NULL argument");
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || !rho[i] || !phi[i])
+      return fail(FSP_ERR_INVALID_ARG, std::string(who) + ": NULL entry " + std::to_string(i));
+    if (!plans[i]->ready)
+      return fail(FSP_ERR_NOT_READY, std::string(who) + ": plan " + std::to_string(i) + " is not ready");
+    if (plans[i]->device != plans[0]->device)
+      return fail(FSP_ERR_INVALID_ARG, std::string(who) + ": plans on different devices");
+    for (int j = 0; j < i; ++j)
+      if (plans[j] == plans[i] || plans[j]->work == plans[i]->work)
+        return fail(FSP_ERR_INVALID_ARG, std::string(who) + ": two entries share a workspace");
+  }
   return FSP_OK;
 }
 
@@ -521,29 +602,13 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
 
 fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const* rho, void* const* phi,
                              void* stream) {
-  if (count < 0) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: negative count");
-  if (count == 0) return FSP_OK;
-  if (!plans || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: NULL argument");
-  for (int i = 0; i < count; ++i) {
-    if (!plans[i] || !rho[i] || !phi[i])
-      return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: NULL entry " + std::to_string(i));
-    if (!plans[i]->ready)
-      return fail(FSP_ERR_NOT_READY, "fsp_solve_batched: plan " + std::to_string(i) + " is not ready");
-    if (plans[i]->device != plans[0]->device)
-      return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: plans on different devices");
-    for (int j = 0; j < i; ++j)
-      if (plans[j] == plans[i] || plans[j]->work == plans[i]->work)
-        return fail(FSP_ERR_INVALID_ARG, "fsp_solve_batched: two entries share a workspace");
-  }
+  fsp_status st = check_batch("fsp_solve_batched", count, plans, rho, phi);
+  if (st != FSP_OK || count == 0) return st;
   DeviceGuard guard;
   hipError_t e = guard.enter(plans[0]->device);
   if (e != hipSuccess) return fail_hip(e, "fsp_solve_batched: hipSetDevice");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  for (int i = 0; i < count; ++i) {
-    fsp_status st = solve_one(plans[i], rho[i], phi[i], s);
-    if (st != FSP_OK) return st;
-  }
-  return FSP_OK;
+  return enqueue_batch(count, plans, rho, phi, &s, 1);
 }
 
 fsp_status fsp_plan_destroy(fsp_plan p) {
@@ -554,6 +619,110 @@ fsp_status fsp_plan_destroy(fsp_plan p) {
     release_buffers(p);
   }
   delete p;
+  return FSP_OK;
+}
+
+}  // extern "C"
+
+struct fsp_batch_s {
+  std::vector<fsp_plan> plans;
+  std::vector<const void*> rho;
+  std::vector<void*> phi;
+  int device = 0;
+  int branches = 4;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// Capture the grouped launches of a batch as one graph whose launch groups run
+// on parallel branches.
+hipError_t capture_batch(fsp_batch_s* b) {
+  const int nb = b->branches;
+  hipStream_t cs = nullptr;
+  std::vector<hipStream_t> side(nb, nullptr);
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join(nb, nullptr);
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+  bool capturing = false;
+  if (e == hipSuccess) {
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    capturing = e == hipSuccess;
+  }
+  if (e == hipSuccess) e = hipEventRecord(fork, cs);
+  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[i], fork, 0);
+  if (e == hipSuccess) {
+    fsp_status st = enqueue_batch((int)b->plans.size(), b->plans.data(), b->rho.data(), b->phi.data(), side.data(), nb);
+    if (st != FSP_OK) e = hipErrorLaunchFailure;
+  }
+  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipEventRecord(join[i], side[i]);
+  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(cs, join[i], 0);
+  if (capturing) {
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) {
+      b->graph = g;
+      e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  for (auto ev : join)
+    if (ev) (void)hipEventDestroy(ev);
+  if (fork) (void)hipEventDestroy(fork);
+  for (auto st : side)
+    if (st) (void)hipStreamDestroy(st);
+  if (cs) (void)hipStreamDestroy(cs);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+fsp_status fsp_batch_create(int count, const fsp_plan* plans, const void* const* rho, void* const* phi,
+                            fsp_batch* out) {
+  if (!out) return fail(FSP_ERR_INVALID_ARG, "fsp_batch_create: NULL out");
+  *out = nullptr;
+  if (count <= 0) return fail(FSP_ERR_INVALID_ARG, "fsp_batch_create: count must be positive");
+  fsp_status st = check_batch("fsp_batch_create", count, plans, rho, phi);
+  if (st != FSP_OK) return st;
+  fsp_batch_s* b = new (std::nothrow) fsp_batch_s();
+  if (!b) return fail(FSP_ERR_OUT_OF_MEMORY, "fsp_batch_create: host allocation failed");
+  b->plans.assign(plans, plans + count);
+  b->rho.assign(rho, rho + count);
+  b->phi.assign(phi, phi + count);
+  b->device = plans[0]->device;
+  *out = b;
+  return FSP_OK;
+}
+
+fsp_status fsp_batch_launch(fsp_batch b, void* stream) {
+  if (!b) return fail(FSP_ERR_INVALID_ARG, "fsp_batch_launch: NULL batch");
+  DeviceGuard guard;
+  hipError_t e = guard.enter(b->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_batch_launch: hipSetDevice");
+  if (!b->exec) {
+    e = capture_batch(b);
+    if (e != hipSuccess) return fail_hip(e, "fsp_batch_launch: graph capture");
+  }
+  e = hipGraphLaunch(b->exec, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail_hip(e, "fsp_batch_launch: hipGraphLaunch");
+  return FSP_OK;
+}
+
+fsp_status fsp_batch_destroy(fsp_batch b) {
+  if (!b) return fail(FSP_ERR_INVALID_ARG, "fsp_batch_destroy: NULL batch");
+  DeviceGuard guard;
+  (void)guard.enter(b->device);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
   return FSP_OK;
 }
 

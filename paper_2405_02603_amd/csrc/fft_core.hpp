@@ -268,6 +268,17 @@ struct Dft<32, INV, T> {
   }
 };
 
+// ---------------------------------------------------------------- barriers
+// Workgroup barrier for LDS reuse only: waits for this wave's LDS traffic,
+// then synchronises the waves.  Global loads and stores stay in flight (the
+// kernels never exchange data through global memory inside a launch), so a
+// prefetch issued before the barrier keeps overlapping with the work after it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // ---------------------------------------------------------------- stages
 // Two consecutive complex values of the twiddle table in one load where the type allows.
 template <typename T>
@@ -336,7 +347,7 @@ __device__ __forceinline__ void lds_stage(cx<T>* lds, const cx<T>* __restrict__ 
       for (int r = 0; r < R; ++r) v[j][r] = lds[idx(b + r * NB)];
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int b = q + NQ * j;
@@ -348,7 +359,7 @@ __device__ __forceinline__ void lds_stage(cx<T>* lds, const cx<T>* __restrict__ 
       for (int m = 0; m < R; ++m) lds[idx(base + m * NS)] = v[j][m];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 template <typename T, int L, bool REV, int S, int SEND, int NQ, bool INV, class IDX>

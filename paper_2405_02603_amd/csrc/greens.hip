@@ -119,16 +119,24 @@ __global__ __launch_bounds__(256) void k_contract_rotate(const double* __restric
   }
 }
 
-// out[(k0 (n1+1) + k1) * pitch + k2] = scale * G[(k0 (n1+1) + k1) (n2+1) + k2]
+// Store the octant G[k0][k1][k2] (float64, dense) scaled, in the blocked layout
+// out[((k1 * tiles + k2 / tile) * (n0 + 1) + k0) * tile + k2 % tile]; slots of
+// the last tile beyond k2 = n2 are zero.
 template <typename T>
 __global__ __launch_bounds__(256) void k_store_octant(const double* __restrict__ G, T* __restrict__ out, int n0,
-                                                      int n1, int n2, int pitch, double scale) {
-  const long long total = (long long)(n0 + 1) * (n1 + 1) * (n2 + 1);
+                                                      int n1, int n2, int tile, double scale) {
+  const int tiles = (n2 + 1 + tile - 1) / tile;
+  const long long total = (long long)(n1 + 1) * tiles * (n0 + 1) * tile;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
-  const int k2 = (int)(i % (n2 + 1));
-  const long long rowi = i / (n2 + 1);
-  out[rowi * pitch + k2] = (T)(scale * G[i]);
+  const int c = (int)(i % tile);
+  long long t = i / tile;
+  const int k0 = (int)(t % (n0 + 1));
+  t /= (n0 + 1);
+  const int tl = (int)(t % tiles);
+  const int k1 = (int)(t / tiles);
+  const int k2 = tl * tile + c;
+  out[i] = k2 <= n2 ? (T)(scale * G[((long long)k0 * (n1 + 1) + k1) * (n2 + 1) + k2]) : T(0);
 }
 
 // ------------------------------------------------------------------ host side
@@ -155,15 +163,16 @@ hipError_t greens_contract(const double* X, double* Y, const double* C, int nout
   return hipGetLastError();
 }
 
-hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int pitch, double scale,
+hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int tile, double scale,
                                hipStream_t s) {
-  const long long total = (long long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
+  const long long tiles = (n[2] + 1 + tile - 1) / tile;
+  const long long total = (long long)(n[1] + 1) * tiles * (n[0] + 1) * tile;
   if (f64)
     hipLaunchKernelGGL(k_store_octant<double>, dim3(grid1(total)), dim3(256), 0, s, G, (double*)out, n[0], n[1],
-                       n[2], pitch, scale);
+                       n[2], tile, scale);
   else
     hipLaunchKernelGGL(k_store_octant<float>, dim3(grid1(total)), dim3(256), 0, s, G, (float*)out, n[0], n[1],
-                       n[2], pitch, scale);
+                       n[2], tile, scale);
   return hipGetLastError();
 }
 

@@ -2,7 +2,9 @@
 #include "solve_launch.hpp"
 
 namespace fsp {
-hipError_t solve_f32(const SolveGeom& g, const void* rho, void* phi, int first, int last, hipStream_t s) {
-  return launch_solve<float>(g, rho, phi, first, last, s);
+hipError_t solve_f32(const SolveGeom& g, int first, int last, hipStream_t s) {
+  return launch_solve<float>(g, first, last, s);
 }
+// Column tile of the axis-0 pass for pencil length L (the Green's octant is stored in such tiles).
+int conv_tile_f32(int L) { return col_tiles<float>(L); }
 }  // namespace fsp

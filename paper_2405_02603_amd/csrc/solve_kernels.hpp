@@ -32,23 +32,27 @@
 
 namespace fsp {
 
+// Up to MAX_ITEMS independent solves of one shape share a launch; blockIdx.y
+// selects the item, whose buffers are passed by value in the kernel arguments.
+constexpr int MAX_ITEMS = 16;
+
 struct ColArgs {
-  void* data;                 // S
-  const void* ghat;           // P3: Green's octant [n0+1][n1+1][Pg] (solve precision)
+  void* data[MAX_ITEMS];      // S of each item
+  const void* ghat[MAX_ITEMS];  // P3: Green's octant of each item, blocked [n1+1][tiles][n0+1][TC]
   const void* tw;             // twiddle table of this pencil length
   long long row_stride;       // complex elements between consecutive pencil rows
   long long outer_stride;     // complex elements between consecutive outer indices
   int col0;                   // first column handled by this launch
   int ncols;                  // end of the valid columns (n2 + 1 or a chunk end)
   int ntiles;                 // column tiles per outer index
+  int nouter;                 // outer indices (P2/P4: n0; P3: n1 + 1 pairs)
   int n1;                     // P3: n1 (pairs k1 and 2 n1 - k1 share a Green's row)
-  long long g_row_stride;     // P3: reals between Green's rows k0
-  long long g_k1_stride;      // P3: reals between Green's rows k1
+  long long g_k1_stride;      // P3: reals between Green's blocks k1 (tiles (n0+1) TC)
 };
 
 struct RowArgs {
-  const void* in;
-  void* out;
+  const void* in[MAX_ITEMS];
+  void* out[MAX_ITEMS];
   const void* tw;             // twiddles of length n2, then exp(-i pi k / n2), k in [0, n2]
   int nrows;                  // n0 * n1
   int n1;
@@ -59,6 +63,21 @@ struct RowArgs {
 template <typename T>
 __device__ __forceinline__ cx<T> czero() { return {T(0), T(0)}; }
 
+// LDS slot of element e of a row in the row passes: one pad slot after every
+// 16 elements, so Stockham writes at strides of 16 or 32 elements fall on
+// distinct banks.
+__host__ __device__ constexpr int row_slot(int e) { return e + (e >> 4); }
+__host__ __device__ constexpr int row_pitch(int LC) { return row_slot(LC) + 1; }
+
+// Pencil of thread column c: block b covers TC adjacent columns of outer index b / ntiles.
+template <int TC>
+__device__ __forceinline__ void place_column(const ColArgs& a, int c, int& col, int& outer, bool& ok) {
+  const int tile = blockIdx.x % a.ntiles;
+  outer = blockIdx.x / a.ntiles;
+  col = a.col0 + tile * TC + c;
+  ok = col < a.ncols;
+}
+
 // ----------------------------------------------------------------- P2 / P4
 template <typename T, int L, int TC, int NQ, bool INV>
 __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
@@ -66,13 +85,12 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
   __shared__ cx<T> lds[K > 1 ? L * TC : 1];
   const int tid = threadIdx.x;
   const int c = tid % TC, q = tid / TC;
-  const int tile = blockIdx.x % a.ntiles;
-  const long long outer = blockIdx.x / a.ntiles;
-  const int col = a.col0 + tile * TC + c;
-  const bool cok = col < a.ncols;
-  cx<T>* base = reinterpret_cast<cx<T>*>(a.data) + outer * a.outer_stride + col;
+  int col, outer;
+  bool cok;
+  place_column<TC>(a, c, col, outer, cok);
+  cx<T>* base = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)outer * a.outer_stride + col;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
-  const long long rs = a.row_stride;
+  const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
   auto idx = [c](int row) { return row * TC + c; };
   constexpr bool REV = INV;
   using F = FirstStage<L, REV, NQ>;
@@ -87,7 +105,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
     for (int r = 0; r < F::R; ++r) {
       // forward: rows >= L/2 are the zero padding and are never read
       const bool pad = !INV && r >= F::R / 2;
-      v[j][r] = (ok && !pad) ? base[(long long)(b + r * F::NB) * rs] : czero<T>();
+      v[j][r] = (ok && !pad) ? base[(b + r * F::NB) * rs] : czero<T>();
     }
     Dft<F::R, INV, T>::run(v[j]);
   }
@@ -98,12 +116,12 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
       if (cok && ((F::NB % NQ == 0) || b < F::NB)) {
 #pragma unroll
         for (int m = 0; m < F::R; ++m)
-          if (!INV || m < F::R / 2) base[(long long)(b + m * F::NB) * rs] = v[j][m];
+          if (!INV || m < F::R / 2) base[(b + m * F::NB) * rs] = v[j][m];
       }
     }
   } else {
     write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
-    __syncthreads();
+    lds_barrier();
     lds_stages<T, L, REV, 1, K - 1, NQ, INV>(lds, tw, q, idx);
     using Ls = LastStage<L, REV, NQ>;
     static_assert(!INV || Ls::R % 2 == 0, "inverse plans end with an even radix");
@@ -115,7 +133,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
       if (cok && ((Ls::NB % NQ == 0) || b < Ls::NB)) {
 #pragma unroll
         for (int m = 0; m < Ls::R; ++m)
-          if (!INV || m < Ls::R / 2) base[(long long)(b + m * Ls::NB) * rs] = w[j][m];
+          if (!INV || m < Ls::R / 2) base[(b + m * Ls::NB) * rs] = w[j][m];
       }
     }
   }
@@ -128,19 +146,20 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   __shared__ cx<T> lds[K > 1 ? L * TC : 1];
   const int tid = threadIdx.x;
   const int c = tid % TC, q = tid / TC;
-  const int tile = blockIdx.x % a.ntiles;
-  const int p = blockIdx.x / a.ntiles;  // k1 in [0, n1]; also handles 2 n1 - k1
-  const int col = a.col0 + tile * TC + c;
-  const bool cok = col < a.ncols;
+  int col, p;  // p: k1 in [0, n1]; the thread also handles 2 n1 - p
+  bool cok;
+  place_column<TC>(a, c, col, p, cok);
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
-  const long long rs = a.row_stride;
+  const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
   auto idx = [c](int row) { return row * TC + c; };
   using F = FirstStage<L, false, NQ>;   // forward, first stage
   using Lf = LastStage<L, false, NQ>;   // forward, last stage == inverse, first stage
   static_assert(F::R % 2 == 0, "forward plans start with an even radix");
 
-  // Green's values for the rows this thread holds after the forward transform.
-  const T* g = reinterpret_cast<const T*>(a.ghat) + (long long)p * a.g_k1_stride + col;
+  // Green's values for the rows this thread holds after the forward transform;
+  // the octant is stored in column tiles of TC, so a tile's rows are contiguous.
+  const T* g = reinterpret_cast<const T*>(a.ghat[blockIdx.y]) + (long long)p * a.g_k1_stride +
+               (long long)(col / TC) * (L / 2 + 1) * TC + (col % TC);
   T gv[Lf::J][Lf::R];
 #pragma unroll
   for (int j = 0; j < Lf::J; ++j) {
@@ -150,23 +169,34 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
     for (int m = 0; m < Lf::R; ++m) {
       const int k0 = b + m * Lf::NB;
       const int kf = k0 <= L / 2 ? k0 : L - k0;
-      gv[j][m] = ok ? g[(long long)kf * a.g_row_stride] : T(0);
+      gv[j][m] = ok ? g[kf * TC] : T(0);
     }
   }
 
-  const int npass = (p == 0 || p == a.n1) ? 1 : 2;
-  for (int pass = 0; pass < npass; ++pass) {
-    const int k1 = pass == 0 ? p : 2 * a.n1 - p;
-    cx<T>* base = reinterpret_cast<cx<T>*>(a.data) + (long long)k1 * a.outer_stride + col;
-    if (pass) __syncthreads();
-    cx<T> v[F::J][F::R];
+  // k1 = p and its partner 2 n1 - p share the Green's rows; p = 0 and p = n1 have no partner.
+  // k1 = p and its partner 2 n1 - p share the Green's rows; p = 0 and p = n1
+  // have no partner.  Both pencil sets are loaded before either is
+  // transformed, so the second set's loads overlap the first set's work.
+  using Li = LastStage<L, true, NQ>;
+  static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
+  const bool two = !(p == 0 || p == a.n1);
+  cx<T>* base_a = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)p * a.outer_stride + col;
+  cx<T>* base_b = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)(2 * a.n1 - p) * a.outer_stride + col;
+  auto load_set = [&](const cx<T>* base, bool on, cx<T> (&raw)[F::J][F::R / 2]) {
 #pragma unroll
     for (int j = 0; j < F::J; ++j) {
       const int b = q + NQ * j;
-      const bool ok = cok && ((F::NB % NQ == 0) || b < F::NB);
+      const bool ok = on && cok && ((F::NB % NQ == 0) || b < F::NB);
 #pragma unroll
-      for (int r = 0; r < F::R; ++r)
-        v[j][r] = (ok && r < F::R / 2) ? base[(long long)(b + r * F::NB) * rs] : czero<T>();
+      for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? base[(b + r * F::NB) * rs] : czero<T>();
+    }
+  };
+  auto run_set = [&](cx<T>* base, const cx<T> (&raw)[F::J][F::R / 2]) {
+    cx<T> v[F::J][F::R];
+#pragma unroll
+    for (int j = 0; j < F::J; ++j) {
+#pragma unroll
+      for (int r = 0; r < F::R; ++r) v[j][r] = r < F::R / 2 ? raw[j][r] : czero<T>();
       Dft<F::R, false, T>::run(v[j]);
     }
     if constexpr (K == 1) {
@@ -178,12 +208,12 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
           for (int m = 0; m < F::R; ++m) v[j][m] = cscale(v[j][m], gv[j][m]);
           Dft<F::R, true, T>::run(v[j]);
 #pragma unroll
-          for (int m = 0; m < F::R / 2; ++m) base[(long long)(b + m * F::NB) * rs] = v[j][m];
+          for (int m = 0; m < F::R / 2; ++m) base[(b + m * F::NB) * rs] = v[j][m];
         }
       }
     } else {
       write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
-      __syncthreads();
+      lds_barrier();
       lds_stages<T, L, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
       cx<T> w[Lf::J][Lf::R];
       lds_last_stage<T, L, false, NQ, false>(lds, tw, q, idx, w);
@@ -194,12 +224,10 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
         for (int m = 0; m < Lf::R; ++m) w[j][m] = cscale(w[j][m], gv[j][m]);
         Dft<Lf::R, true, T>::run(w[j]);
       }
-      __syncthreads();
+      lds_barrier();
       write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, w, q, idx);
-      __syncthreads();
+      lds_barrier();
       lds_stages<T, L, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
-      using Li = LastStage<L, true, NQ>;
-      static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
       cx<T> u[Li::J][Li::R];
       lds_last_stage<T, L, true, NQ, true>(lds, tw, q, idx, u);
 #pragma unroll
@@ -207,10 +235,18 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
         const int b = q + NQ * j;
         if (cok && ((Li::NB % NQ == 0) || b < Li::NB)) {
 #pragma unroll
-          for (int m = 0; m < Li::R / 2; ++m) base[(long long)(b + m * Li::NB) * rs] = u[j][m];
+          for (int m = 0; m < Li::R / 2; ++m) base[(b + m * Li::NB) * rs] = u[j][m];
         }
       }
     }
+  };
+  cx<T> raw_a[F::J][F::R / 2], raw_b[F::J][F::R / 2];
+  load_set(base_a, true, raw_a);
+  load_set(base_b, two, raw_b);
+  run_set(base_a, raw_a);
+  if (two) {
+    lds_barrier();
+    run_set(base_b, raw_b);
   }
 }
 
@@ -221,15 +257,15 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
 template <typename T, int LC, int TR, int NQ>
 __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
   constexpr int K = plan_len(LC);
-  constexpr int LP = LC + 1;
+  constexpr int LP = row_pitch(LC);
   __shared__ cx<T> lds[TR * LP];
   const int tid = threadIdx.x;
   const int q = tid % NQ, c = tid / NQ;
   const int row = blockIdx.x * TR + c;
   const bool rok = row < a.nrows;
-  const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in) + (long long)row * (LC / 2);
+  const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in[blockIdx.y]) + (long long)row * (LC / 2);
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
-  auto idx = [c](int e) { return c * LP + e; };
+  auto idx = [c](int e) { return c * LP + row_slot(e); };
   using F = FirstStage<LC, false, NQ>;
   static_assert(F::R % 2 == 0, "forward plans start with an even radix");
 
@@ -246,12 +282,12 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
     write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
   } else {
     write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
-    __syncthreads();
+    lds_barrier();
     lds_stages<T, LC, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
     using Ls = LastStage<LC, false, NQ>;
     cx<T> w[Ls::J][Ls::R];
     lds_last_stage<T, LC, false, NQ, false>(lds, tw, q, idx, w);
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int j = 0; j < Ls::J; ++j) {
       const int b = q + NQ * j;
@@ -261,11 +297,11 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
       }
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (!rok) return;
   const cx<T>* pp = tw + tw_size(LC);
   const int i0 = row / a.n1, i1 = row - i0 * a.n1;
-  cx<T>* out = reinterpret_cast<cx<T>*>(a.out) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
+  cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
   constexpr int JO = (LC + 1 + NQ - 1) / NQ;
 #pragma unroll
   for (int j = 0; j < JO; ++j) {
@@ -288,18 +324,18 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
 template <typename T, int LC, int TR, int NQ>
 __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
   constexpr int K = plan_len(LC);
-  constexpr int LP = LC + 1;
+  constexpr int LP = row_pitch(LC);
   __shared__ cx<T> lds[TR * LP];
   const int tid = threadIdx.x;
   const int q = tid % NQ, c = tid / NQ;
   const int row = blockIdx.x * TR + c;
   const bool rok = row < a.nrows;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
-  auto idx = [c](int e) { return c * LP + e; };
+  auto idx = [c](int e) { return c * LP + row_slot(e); };
   {
     const int i0 = row / a.n1, i1 = row - i0 * a.n1;
     const cx<T>* in =
-        reinterpret_cast<const cx<T>*>(a.in) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
+        reinterpret_cast<const cx<T>*>(a.in[blockIdx.y]) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
     constexpr int JI = (LC + 1 + NQ - 1) / NQ;
 #pragma unroll
     for (int j = 0; j < JI; ++j) {
@@ -307,7 +343,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
       if (k <= LC) lds[idx(k)] = rok ? in[k] : czero<T>();
     }
   }
-  __syncthreads();
+  lds_barrier();
   const cx<T>* pp = tw + tw_size(LC);
   using F = FirstStage<LC, true, NQ>;
   cx<T> v[F::J][F::R];
@@ -327,7 +363,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
       Dft<F::R, true, T>::run(v[j]);
     }
   }
-  cx<T>* out = reinterpret_cast<cx<T>*>(a.out) + (long long)row * (LC / 2);
+  cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)row * (LC / 2);
   if constexpr (K == 1) {
     static_assert(F::R % 2 == 0, "inverse plans end with an even radix");
     if (rok) {
@@ -341,9 +377,9 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
       }
     }
   } else {
-    __syncthreads();
+    lds_barrier();
     write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
-    __syncthreads();
+    lds_barrier();
     lds_stages<T, LC, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
     using Li = LastStage<LC, true, NQ>;
     static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");

@@ -33,7 +33,7 @@ __host__ __device__ constexpr TileCfg col_cfg(int L) {
   }
 }
 
-// Row passes (pencil length LC = n2 complex, contiguous rows).  LDS = TR (LC + 1) sizeof(cx<T>).
+// Row passes (pencil length LC = n2 complex, contiguous rows).  LDS = TR row_pitch(LC) sizeof(cx<T>).
 template <typename T>
 __host__ __device__ constexpr TileCfg row_cfg(int LC) {
   constexpr bool d = sizeof(T) == 8;
@@ -60,13 +60,13 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC) {
   X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
 
 template <typename T>
-hipError_t launch_p1(int LC, const RowArgs& a, hipStream_t s) {
+hipError_t launch_p1(int LC, const RowArgs& a, int items, hipStream_t s) {
   switch (LC) {
 #define FSP_CASE(LV)                                                                        \
   case LV: {                                                                                \
     constexpr TileCfg c = row_cfg<T>(LV);                                                   \
     const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                   \
-    hipLaunchKernelGGL((k_row_r2c<T, LV, c.tiles, c.nq>), dim3(blocks), dim3(c.tiles * c.nq), 0, s, a); \
+    hipLaunchKernelGGL((k_row_r2c<T, LV, c.tiles, c.nq>), dim3(blocks, items), dim3(c.tiles * c.nq), 0, s, a); \
     break;                                                                                  \
   }
     FSP_ROW_LENGTHS(FSP_CASE)
@@ -77,13 +77,13 @@ hipError_t launch_p1(int LC, const RowArgs& a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_p5(int LC, const RowArgs& a, hipStream_t s) {
+hipError_t launch_p5(int LC, const RowArgs& a, int items, hipStream_t s) {
   switch (LC) {
 #define FSP_CASE(LV)                                                                        \
   case LV: {                                                                                \
     constexpr TileCfg c = row_cfg<T>(LV);                                                   \
     const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                   \
-    hipLaunchKernelGGL((k_row_c2r<T, LV, c.tiles, c.nq>), dim3(blocks), dim3(c.tiles * c.nq), 0, s, a); \
+    hipLaunchKernelGGL((k_row_c2r<T, LV, c.tiles, c.nq>), dim3(blocks, items), dim3(c.tiles * c.nq), 0, s, a); \
     break;                                                                                  \
   }
     FSP_ROW_LENGTHS(FSP_CASE)
@@ -106,12 +106,12 @@ int col_tiles(int L) {
 
 // nouter: outer pencils groups (P2/P4: n0; P3: n1 + 1 pairs)
 template <typename T>
-hipError_t launch_col(int L, bool inverse, bool conv, const ColArgs& a, int nouter, hipStream_t s) {
+hipError_t launch_col(int L, bool inverse, bool conv, const ColArgs& a, int items, hipStream_t s) {
   switch (L) {
 #define FSP_CASE(LV)                                                                              \
   case LV: {                                                                                      \
     constexpr TileCfg c = col_cfg<T>(LV);                                                         \
-    const dim3 grid((unsigned)(nouter * a.ntiles));                                               \
+    const dim3 grid((unsigned)(a.nouter * a.ntiles), (unsigned)items);                            \
     const dim3 block(c.tiles * c.nq);                                                             \
     if (conv)                                                                                     \
       hipLaunchKernelGGL((k_col_conv<T, LV, c.tiles, c.nq>), grid, block, 0, s, a);               \
@@ -128,8 +128,9 @@ hipError_t launch_col(int L, bool inverse, bool conv, const ColArgs& a, int nout
   return hipGetLastError();
 }
 
-// Geometry of one solve, filled by the plan.
+// Geometry of up to MAX_ITEMS solves of one shape, filled by the plans.
 struct SolveGeom {
+  int items;                 // solves in this group (1 .. MAX_ITEMS)
   int n0, n1, n2;
   int pitch;                 // P
   long long plane;           // complex elements between S planes i0 (>= 2 n1 P)
@@ -137,13 +138,15 @@ struct SolveGeom {
   const void* tw_row;        // twiddles, length n2 (+ split table)
   const void* tw_c1;         // twiddles, length 2 n1
   const void* tw_c0;         // twiddles, length 2 n0
-  const void* ghat;          // octant [n0+1][n1+1][P]
-  void* work;                // S
+  const void* ghat[MAX_ITEMS];  // octant of each item, blocked [n1+1][tiles][n0+1][TC of P3]
+  void* work[MAX_ITEMS];        // S of each item
+  const void* rho[MAX_ITEMS];
+  void* phi[MAX_ITEMS];
 };
 
 // Passes first..last of one solve (0 = P1 ... 4 = P5).
 template <typename T>
-hipError_t launch_solve(const SolveGeom& g, const void* rho, void* phi, int first, int last, hipStream_t s) {
+hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) {
   const long long P = g.pitch;
   const long long plane = g.plane;  // complex elements per S plane i0
   RowArgs ra{};
@@ -154,22 +157,28 @@ hipError_t launch_solve(const SolveGeom& g, const void* rho, void* phi, int firs
   ra.tw = g.tw_row;
   // P2 / P4: pencils along axis 1; outer = i0
   ColArgs ca{};
-  ca.data = g.work;
+  for (int i = 0; i < g.items; ++i) ca.data[i] = g.work[i];
   ca.ncols = g.n2 + 1;
   ca.row_stride = P;
   ca.outer_stride = plane;
+  ca.nouter = g.n0;
   ca.tw = g.tw_c1;
   // P3: pencils along axis 0; outer = k1 pairs
   ColArgs cc{};
-  cc.data = g.work;
-  cc.ghat = g.ghat;
+  for (int i = 0; i < g.items; ++i) {
+    cc.data[i] = g.work[i];
+    cc.ghat[i] = g.ghat[i];
+  }
   cc.ncols = g.n2 + 1;
   cc.row_stride = plane;
   cc.outer_stride = P;
+  cc.nouter = g.n1 + 1;
   cc.tw = g.tw_c0;
   cc.n1 = g.n1;
-  cc.g_k1_stride = P;
-  cc.g_row_stride = (long long)(g.n1 + 1) * P;
+  {
+    const long long t0 = col_tiles<T>(2 * g.n0);
+    cc.g_k1_stride = (g.n2 + 1 + t0 - 1) / t0 * (g.n0 + 1) * t0;
+  }
   const int tc1 = col_tiles<T>(2 * g.n1), tc0 = col_tiles<T>(2 * g.n0);
   const int ncols = g.n2 + 1;
   auto set_cols = [&](ColArgs& c, int tcw, int c0, int c1) {
@@ -180,16 +189,20 @@ hipError_t launch_solve(const SolveGeom& g, const void* rho, void* phi, int firs
   auto run = [&](int pass, int c0, int c1) -> hipError_t {
     switch (pass) {
       case 0:
-        ra.in = rho;
-        ra.out = g.work;
-        return launch_p1<T>(g.n2, ra, s);
-      case 1: set_cols(ca, tc1, c0, c1); return launch_col<T>(2 * g.n1, false, false, ca, g.n0, s);
-      case 2: set_cols(cc, tc0, c0, c1); return launch_col<T>(2 * g.n0, false, true, cc, g.n1 + 1, s);
-      case 3: set_cols(ca, tc1, c0, c1); return launch_col<T>(2 * g.n1, true, false, ca, g.n0, s);
+        for (int i = 0; i < g.items; ++i) {
+          ra.in[i] = g.rho[i];
+          ra.out[i] = g.work[i];
+        }
+        return launch_p1<T>(g.n2, ra, g.items, s);
+      case 1: set_cols(ca, tc1, c0, c1); return launch_col<T>(2 * g.n1, false, false, ca, g.items, s);
+      case 2: set_cols(cc, tc0, c0, c1); return launch_col<T>(2 * g.n0, false, true, cc, g.items, s);
+      case 3: set_cols(ca, tc1, c0, c1); return launch_col<T>(2 * g.n1, true, false, ca, g.items, s);
       case 4:
-        ra.in = g.work;
-        ra.out = phi;
-        return launch_p5<T>(g.n2, ra, s);
+        for (int i = 0; i < g.items; ++i) {
+          ra.in[i] = g.work[i];
+          ra.out[i] = g.phi[i];
+        }
+        return launch_p5<T>(g.n2, ra, g.items, s);
       default: return hipErrorInvalidValue;
     }
   };

@@ -112,13 +112,16 @@ def test_buffer_sizes_and_model_bytes(lib, prec, rb, n):
     assert st == _lib.FSP_OK
     g, w = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.fsp_plan_bytes(h, ctypes.byref(g), ctypes.byref(w)) == _lib.FSP_OK
-    off, pitch = ctypes.c_size_t(), ctypes.c_int()
-    assert lib.fsp_plan_ghat_layout(h, ctypes.byref(off), ctypes.byref(pitch)) == _lib.FSP_OK
+    off, tile = ctypes.c_size_t(), ctypes.c_int()
+    assert lib.fsp_plan_ghat_layout(h, ctypes.byref(off), ctypes.byref(tile)) == _lib.FSP_OK
     n0, n1, n2 = n
-    assert pitch.value >= n2 + 1 and (pitch.value * 2 * rb) % 128 == 0
+    t = tile.value
+    assert t >= 1 and (t & (t - 1)) == 0
     assert off.value % 256 == 0
-    assert g.value >= off.value + (n0 + 1) * (n1 + 1) * pitch.value * rb
-    assert w.value >= n0 * 2 * n1 * pitch.value * 2 * rb
+    tiles = (n2 + 1 + t - 1) // t
+    assert g.value >= off.value + (n1 + 1) * tiles * (n0 + 1) * t * rb
+    pitch = n2 + 1 + (-(n2 + 1)) % (128 // (2 * rb))
+    assert w.value >= n0 * 2 * n1 * pitch * 2 * rb
     mb = ctypes.c_double()
     assert lib.fsp_plan_model_bytes(h, ctypes.byref(mb)) == _lib.FSP_OK
     # five passes: 2 N^3 + 24 (N2+1) N0 N1 + (N0+1)(N1+1)(N2+1) reals

@@ -1,0 +1,106 @@
+"""GPU: batched solves (grouped launches, captured graphs) equal their solo solves.
+
+Solves of one shape use the same kernels whether alone or grouped, so the
+results must agree bit for bit; a graph is replayed several times with eager
+work in between and every replay is checked against the eager result.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+from gpu_util import reference, rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _mix(count, seed, sizes=(32, 48, 64, 96, 128)):
+    items = W.batch_mix(seed=seed, count=count, sizes=sizes)
+    return items
+
+
+def _plans_and_inputs(torch, items, prec="f32", kinds=("vico_dct",)):
+    from paper_2405_02603_amd import Plan
+    dt = torch.float32 if prec == "f32" else torch.float64
+    cache = {}
+    plans, rhos, host = [], [], []
+    for i, it in enumerate(items):
+        kind = kinds[i % len(kinds)]
+        key = (it.n, kind)
+        p = Plan(n=it.n, lo=it.lo, hi=it.hi, greens=kind, prec=prec, precompute=False)
+        if key not in cache:
+            p.precompute()
+            cache[key] = p
+        else:
+            p.share_ghat(cache[key])
+        rho = W.source_density(it.n, it.lo, it.hi, it.source)
+        plans.append(p)
+        host.append(rho)
+        rhos.append(to_dev(rho, dt))
+    return plans, rhos, host
+
+
+def test_batched_equals_solo_bitwise(torch_cuda):
+    torch = torch_cuda
+    from paper_2405_02603_amd import solve_batched
+    items = _mix(24, seed=4)
+    plans, rhos, host = _plans_and_inputs(torch, items, kinds=("vico_dct", "hockney"))
+    outs = solve_batched(plans, rhos)
+    torch.cuda.synchronize()
+    for p, r, o in zip(plans, rhos, outs):
+        solo = p.solve(r)
+        torch.cuda.synchronize()
+        assert torch.equal(solo, o)
+    # and the results are right
+    for i in (0, 5, 11):
+        kind = ("vico_dct", "hockney")[i % 2]
+        ref = reference(host[i], kind, items[i].lo, items[i].hi, use_direct=False)
+        assert rel_l2(to_host(outs[i]), ref) <= 1e-6
+
+
+def test_more_than_one_launch_group(torch_cuda):
+    """20 equal-shape solves: more than one launch group of at most 16."""
+    torch = torch_cuda
+    from paper_2405_02603_amd import solve_batched
+    items = _mix(20, seed=9, sizes=(32,))
+    plans, rhos, _ = _plans_and_inputs(torch, items, prec="f64")
+    outs = solve_batched(plans, rhos)
+    torch.cuda.synchronize()
+    for p, r, o in zip(plans, rhos, outs):
+        assert torch.equal(p.solve(r), o)
+
+
+def test_graph_replays_match_eager(torch_cuda):
+    torch = torch_cuda
+    from paper_2405_02603_amd import Batch
+    items = _mix(12, seed=5, sizes=(32, 48, 64))
+    plans, rhos, _ = _plans_and_inputs(torch, items)
+    eager = [p.solve(r) for p, r in zip(plans, rhos)]
+    torch.cuda.synchronize()
+    batch = Batch(plans, rhos)
+    for rep in range(4):
+        for o in batch.outs:
+            o.fill_(float("nan"))
+        # eager work on the same workspaces between replays
+        plans[rep].solve(rhos[rep])
+        batch.launch()
+        torch.cuda.synchronize()
+        for e, o in zip(eager, batch.outs):
+            assert torch.equal(e, o), f"replay {rep}"
+    batch.close()
+
+
+def test_batched_rejects_shared_workspace(torch_cuda):
+    torch = torch_cuda
+    from paper_2405_02603_amd import FspError, Plan, solve_batched
+    p = Plan(n=16, prec="f32")
+    r = torch.zeros((16, 16, 16), device="cuda")
+    with pytest.raises(FspError):
+        solve_batched([p, p], [r, r])

@@ -1,0 +1,83 @@
+"""GPU: the continuous-batching server.
+
+A short Poisson-arrival run with mixed sizes and both Green's functions checks
+that every request completes, that the bytes in flight never exceed the budget,
+that the float64 spot checks agree with the float32 results, and that every
+result served in the mix equals the same request solved alone (same kernels,
+so bit for bit)."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SIZES = (32, 48, 64, 96)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _sources(torch):
+    pool = {}
+    for n in SIZES:
+        rho = W.source_density(n, (-1.0,) * 3, (1.0,) * 3, W.multiblob(seed=n))
+        for dt in (torch.float32, torch.float64):
+            pool[(n, dt)] = torch.from_numpy(rho).to(dt).pin_memory()
+    return pool
+
+
+def _jobs(count, rate, seed, spot_every=10):
+    from paper_2405_02603_amd.serve import Job
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    jobs = []
+    for rid in range(count):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(SIZES[int(rng.integers(0, len(SIZES)))])
+        greens = "hockney" if rng.random() < 0.5 else "vico_dct"
+        jobs.append(Job(rid=rid, t_arrival=t, n=n, greens=greens, spot_check=(rid % spot_every == 3)))
+    return jobs
+
+
+def test_serve_mix_equals_alone(torch_cuda):
+    torch = torch_cuda
+    from paper_2405_02603_amd import Plan
+    from paper_2405_02603_amd.serve import GpuExecutor, Server
+
+    pool = _sources(torch)
+    ex = GpuExecutor(slots=4, source_for=lambda j, dt: pool[(j.n, dt)], keep_results=True)
+    ex.warm([(n, g, p) for n in SIZES for g in ("hockney", "vico_dct") for p in ("f32", "f64")])
+    budget = 1 << 30
+    srv = Server(ex, budget_bytes=budget, slots=4)
+    jobs = _jobs(48, rate=400.0, seed=5)
+    rep = srv.run(jobs)
+    torch.cuda.synchronize()
+    assert rep["done"] == len(jobs), rep
+    assert rep["peak_bytes"] <= budget
+    assert rep["p99_ms"] >= rep["p50_ms"] > 0
+    assert rep["spot_checks"] >= 4
+    assert rep["spot_rel_l2_max"] <= 1e-6
+    for j in jobs:
+        alone = Plan(n=j.n, lo=(-1.0,) * 3, hi=(1.0,) * 3, greens=j.greens, prec="f32")
+        phi = alone.solve(pool[(j.n, torch.float32)].to("cuda"))
+        torch.cuda.synchronize()
+        assert torch.equal(phi, ex.results[j.rid]), f"request {j.rid} differs in the mix"
+
+
+def test_serve_rejects_over_budget(torch_cuda):
+    torch = torch_cuda
+    from paper_2405_02603_amd.serve import GpuExecutor, Job, Server
+
+    pool = _sources(torch)
+    ex = GpuExecutor(slots=2, source_for=lambda j, dt: pool[(j.n, dt)])
+    srv = Server(ex, budget_bytes=8 << 20, slots=2)   # 8 MiB: 32^3 fits, 96^3 does not
+    jobs = [Job(rid=0, t_arrival=0.0, n=96, greens="hockney"), Job(rid=1, t_arrival=0.0, n=32, greens="hockney")]
+    rep = srv.run(jobs)
+    assert jobs[0].status == "rejected"
+    assert jobs[1].status == "done"
+    assert rep["done"] == 1 and rep["rejected"] == 1
