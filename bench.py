@@ -56,6 +56,7 @@ def parse(argv=None):
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--skip-f64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
     ap.add_argument("--workload", default="single", choices=["single", "batch", "serve"],
                     help="single: the 256^3 headline; batch: 64 uneven right-hand sides per graph launch; "
                          "serve: Poisson-arrival serving loop")
@@ -284,6 +285,9 @@ def main(argv=None):
         plan = Plan(n=n, lo=lo, hi=hi, greens=args.greens, prec=prec)
         rho = torch.from_numpy(rho64).to(device="cuda", dtype=dt)
         phi = torch.empty_like(rho)
+        tune = None
+        if not args.no_autotune:
+            tune = plan.autotune(rho, phi, reps=4)   # outside the timed region
         torch.cuda.synchronize()
         ms = time_solves(torch, plan, rho, phi, args.steps, args.warmup)
         pass_ms = time_passes(torch, plan, rho, phi, args.steps)
@@ -297,6 +301,8 @@ def main(argv=None):
             "pass_ms": pass_ms,
             "phi": phi.double().cpu().numpy(),
             "rb": 4 if prec == "f32" else 8,
+            "schedule": plan.schedule,
+            "tune_ms": None if tune is None else {str(k): [round(x, 5) for x in v] for k, v in tune.items()},
         }
         del plan, rho, phi
         torch.cuda.empty_cache()
@@ -334,11 +340,14 @@ def main(argv=None):
         "passes": [{"kernel": PASS_NAMES[i], "ms": round(r32["pass_ms"][i], 5),
                     "GBs": round(pb[i] / (r32["pass_ms"][i] * 1e-3) / 1e9, 1)} for i in range(5)],
         "roofline": roofline,
+        "schedule": r32["schedule"],
+        "autotune_ms": r32["tune_ms"],
     }
     if "f64" in results:
         r64 = results["f64"]
         pb64 = pass_bytes((n, n, n), 8)
         out["fp64"] = {"solves_per_s": round(r64["solves_per_s"], 2), "ms_per_step": round(r64["ms"], 5),
+                       "schedule": r64["schedule"], "autotune_ms": r64["tune_ms"],
                        "hbm_frac_model": round(r64["hbm_frac_model"], 4),
                        "passes": [{"kernel": PASS_NAMES[i], "ms": round(r64["pass_ms"][i], 5),
                                    "GBs": round(pb64[i] / (r64["pass_ms"][i] * 1e-3) / 1e9, 1)}

@@ -131,6 +131,23 @@ fsp_status fsp_solve(fsp_plan p, const void* rho, void* phi, void* stream);
  * NULL when its pass is outside the range). */
 fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, int last, void* stream);
 
+/* Schedules.  Every pass has NUM_VARIANTS = 3 kernel variants (radix plan,
+ * threads per pencil, tile); variants[i] selects the one for pass i (0..4,
+ * as in fsp_solve_passes).  Results are identical up to rounding order across
+ * variants.  A new plan starts with the schedule last tuned for its grid and
+ * precision in this process (else all zeros). */
+fsp_status fsp_plan_get_schedule(fsp_plan p, int* variants /* [5] */);
+fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants /* [5] */);
+
+/* Time every variant of every pass on this plan's buffers with HIP events
+ * (reps timed launches each, 1 <= reps <= 8, after a warm launch), keep the
+ * fastest per pass in the plan and in the process-wide table used by new
+ * plans of this grid and precision.  rho and phi are as in fsp_solve; on
+ * return phi holds the solve of rho with the tuned schedule.  Synchronises
+ * `stream`.  times_ms (NULL or [5 * 3]) receives the average time of each
+ * variant: times_ms[pass * 3 + variant]. */
+fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* stream, float* times_ms);
+
 /* count independent solves (each with its own plan, and so its own
  * workspace) enqueued on one stream; plans may differ in size, precision and
  * Green's function.  rho[i] / phi[i] as in fsp_solve.  Solves of plans with

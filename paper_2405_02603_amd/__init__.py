@@ -193,6 +193,32 @@ class Plan:
         return out
 
     @property
+    def schedule(self):
+        """Variant of each of the five passes."""
+        arr = (ctypes.c_int * 5)()
+        check(self._lib.fsp_plan_get_schedule(self._h, arr), "fsp_plan_get_schedule")
+        return list(arr)
+
+    @schedule.setter
+    def schedule(self, variants):
+        arr = (ctypes.c_int * 5)(*[int(v) for v in variants])
+        check(self._lib.fsp_plan_set_schedule(self._h, arr), "fsp_plan_set_schedule")
+
+    def autotune(self, rho, out=None, reps: int = 4, stream=None):
+        """Time every pass variant on rho (see fsp_autotune); returns {pass: [ms per variant]}."""
+        torch = _torch()
+        self._check_field(rho, "rho")
+        if out is None:
+            out = torch.empty_like(rho)
+        self._check_field(out, "out")
+        times = (ctypes.c_float * (5 * _lib.NUM_VARIANTS))()
+        with torch.cuda.device(self.device):
+            check(self._lib.fsp_autotune(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                         int(reps), _stream_ptr(stream), times), "fsp_autotune")
+        nv = _lib.NUM_VARIANTS
+        return {p: [times[p * nv + v] for v in range(nv)] for p in range(5)}
+
+    @property
     def handle(self) -> ctypes.c_void_p:
         return self._h
 

@@ -20,6 +20,7 @@ FSP_ERR_NOT_READY = 5
 FSP_ERR_DEVICE = 6
 
 GREENS = {"hockney": 0, "vico": 1, "vico_dct": 2}
+NUM_VARIANTS = 3
 PREC = {"f32": 0, "f64": 1}
 
 # every symbol include/fsp.h declares
@@ -28,6 +29,7 @@ EXPORTS = (
     "fsp_plan_share_ghat", "fsp_precompute", "fsp_solve", "fsp_solve_passes", "fsp_solve_batched", "fsp_plan_destroy",
     "fsp_plan_ghat_layout", "fsp_plan_model_bytes", "fsp_status_str", "fsp_last_error", "fsp_version",
     "fsp_batch_create", "fsp_batch_launch", "fsp_batch_destroy",
+    "fsp_plan_get_schedule", "fsp_plan_set_schedule", "fsp_autotune",
 )
 
 
@@ -77,6 +79,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "fsp_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                      POINTER(c_void_p)]),
         "fsp_batch_launch": (c_int, [P, P]),
+        "fsp_plan_get_schedule": (c_int, [P, POINTER(c_int)]),
+        "fsp_plan_set_schedule": (c_int, [P, POINTER(c_int)]),
+        "fsp_autotune": (c_int, [P, P, P, c_int, P, POINTER(ctypes.c_float)]),
         "fsp_batch_destroy": (c_int, [P]),
         "fsp_plan_ghat_layout": (c_int, [P, POINTER(c_size_t), POINTER(c_int)]),
         "fsp_plan_model_bytes": (c_int, [P, POINTER(c_double)]),

@@ -7,6 +7,10 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <array>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "fft_core.hpp"
@@ -72,12 +76,12 @@ void push_c(std::vector<char>& buf, long double re, long double im) {
 // Twiddles of one pencil length: forward order then reversed order (fft_core.hpp layout):
 // per stage s >= 1 and k in [0, NS): w^(p k) for p = 1, 2, 4, 8, 16, 3, w = exp(-2 pi i / (NS R)).
 template <typename T>
-void append_twiddles(std::vector<char>& buf, int L) {
+void append_twiddles(std::vector<char>& buf, int L, int pid) {
   for (int rev = 0; rev < 2; ++rev) {
-    const int K = fsp::plan_len(L);
+    const int K = fsp::plan_len(L, pid);
     for (int s = 1; s < K; ++s) {
-      const int R = fsp::plan_radix(L, rev != 0, s);
-      const int NS = fsp::plan_ns(L, rev != 0, s);
+      const int R = fsp::plan_radix(L, pid, rev != 0, s);
+      const int NS = fsp::plan_ns(L, pid, rev != 0, s);
       for (int k = 0; k < NS; ++k)
         for (int e = 0; e < fsp::TW_PER_K; ++e) {
           long double c, sn;
@@ -144,7 +148,8 @@ struct fsp_plan_s {
   int gtile = 0;  // column tile of the blocked Green's octant
   long long plane = 0;  // complex elements between S planes i0
   int chunks = 1;       // column chunks for passes 1-3
-  size_t tw_row_off = 0, tw_c1_off = 0, tw_c0_off = 0, oct_off = 0;
+  size_t tw_row_off[fsp::NUM_PLANS]{}, tw_c1_off[fsp::NUM_PLANS]{}, tw_c0_off[fsp::NUM_PLANS]{}, oct_off = 0;
+  int var[5]{};  // schedule variant of each pass
   size_t ghat_bytes = 0, work_bytes = 0, pre_bytes = 0;
   std::vector<char> tw_host;      // image of [0, oct_off) of the Green's buffer
   std::vector<double> cmat_host;  // cosine matrices used by the precompute
@@ -162,22 +167,39 @@ template <typename T>
 void build_twiddles(fsp_plan_s* p) {
   std::vector<char>& b = p->tw_host;
   b.clear();
-  p->tw_row_off = 0;
-  append_twiddles<T>(b, p->n[2]);
-  for (int k = 0; k <= p->n[2]; ++k) {  // split table exp(-i pi k / n2)
-    long double c, s;
-    cis_neg(k, 2LL * p->n[2], &c, &s);
-    push_c<T>(b, c, s);
+  for (int pid = 0; pid < fsp::NUM_PLANS; ++pid) {
+    p->tw_row_off[pid] = b.size();
+    append_twiddles<T>(b, p->n[2], pid);
+    for (int k = 0; k <= p->n[2]; ++k) {  // split table exp(-i pi k / n2)
+      long double c, s;
+      cis_neg(k, 2LL * p->n[2], &c, &s);
+      push_c<T>(b, c, s);
+    }
+    b.resize(align_up(b.size(), 256), 0);
   }
-  b.resize(align_up(b.size(), 256), 0);
-  p->tw_c1_off = b.size();
-  append_twiddles<T>(b, 2 * p->n[1]);
-  b.resize(align_up(b.size(), 256), 0);
-  p->tw_c0_off = b.size();
-  append_twiddles<T>(b, 2 * p->n[0]);
-  b.resize(align_up(b.size(), 256), 0);
+  for (int pid = 0; pid < fsp::NUM_PLANS; ++pid) {
+    p->tw_c1_off[pid] = b.size();
+    append_twiddles<T>(b, 2 * p->n[1], pid);
+    b.resize(align_up(b.size(), 256), 0);
+  }
+  for (int pid = 0; pid < fsp::NUM_PLANS; ++pid) {
+    p->tw_c0_off[pid] = b.size();
+    append_twiddles<T>(b, 2 * p->n[0], pid);
+    b.resize(align_up(b.size(), 256), 0);
+  }
   p->oct_off = b.size();
 }
+
+// Schedules found by the autotuner, per (n0, n1, n2, precision); new plans of a
+// tuned shape start with the tuned schedule.
+struct TuneKey {
+  int n0, n1, n2, prec;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(n0, n1, n2, prec) < std::tie(o.n0, o.n1, o.n2, o.prec);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::array<int, 5>> g_tuned;
 
 double model_bytes(const fsp_plan_s* p) {
   // P1 reads rho, writes (n2+1) n1 n0 complex; P2 reads that, writes 2 n1 (n2+1) n0;
@@ -272,6 +294,12 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     if (const char* e = std::getenv("FSP_CHUNKS")) p->chunks = std::max(1, std::atoi(e));
   }
   p->work_bytes = align_up((size_t)p->n[0] * p->plane * cb, 256);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(TuneKey{p->n[0], p->n[1], p->n[2], d.prec});
+    if (it != g_tuned.end())
+      for (int i = 0; i < 5; ++i) p->var[i] = it->second[i];
+  }
   // the column kernels address a pencil's rows with 32-bit element offsets
   if ((long long)(2 * p->n[0]) * p->plane >= (1LL << 31)) {
     delete p;
@@ -503,9 +531,16 @@ static fsp::SolveGeom group_geom(const fsp_plan_s* p) {
   g.plane = p->plane;
   g.chunks = p->chunks;
   const char* gb = static_cast<const char*>(p->ghat_read);
-  g.tw_row = gb + p->tw_row_off;
-  g.tw_c1 = gb + p->tw_c1_off;
-  g.tw_c0 = gb + p->tw_c0_off;
+  for (int i = 0; i < 5; ++i) g.var[i] = p->var[i];
+  const int pr1 = fsp::row_cfg<float>(p->n[2], p->var[0]).pid, pr5 = fsp::row_cfg<float>(p->n[2], p->var[4]).pid;
+  const int pc2 = fsp::col_cfg<float>(2 * p->n[1], p->var[1]).pid, pc4 = fsp::col_cfg<float>(2 * p->n[1], p->var[3]).pid;
+  const int pc3 = fsp::col_cfg<float>(2 * p->n[0], p->var[2]).pid;
+  for (int i = 0; i < 5; ++i) g.tw_row[i] = g.tw_c1[i] = nullptr;
+  g.tw_row[0] = gb + p->tw_row_off[pr1];
+  g.tw_row[4] = gb + p->tw_row_off[pr5];
+  g.tw_c1[1] = gb + p->tw_c1_off[pc2];
+  g.tw_c1[3] = gb + p->tw_c1_off[pc4];
+  g.tw_c0 = gb + p->tw_c0_off[pc3];
   return g;
 }
 
@@ -518,8 +553,10 @@ static void add_item(fsp::SolveGeom& g, const fsp_plan_s* p, const void* rho, vo
 }
 
 static bool same_shape(const fsp_plan_s* a, const fsp_plan_s* b) {
-  return a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] && a->d.prec == b->d.prec &&
-         a->pitch == b->pitch && a->plane == b->plane && a->chunks == b->chunks;
+  bool same = a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] && a->d.prec == b->d.prec &&
+              a->pitch == b->pitch && a->plane == b->plane && a->chunks == b->chunks;
+  for (int i = 0; i < 5; ++i) same = same && a->var[i] == b->var[i];
+  return same;
 }
 
 static hipError_t run_group(const fsp::SolveGeom& g, bool f64, int first, int last, hipStream_t s) {
@@ -598,6 +635,81 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
   hipError_t e = guard.enter(p->device);
   if (e != hipSuccess) return fail_hip(e, "fsp_solve_passes: hipSetDevice");
   return solve_one(p, rho, phi, reinterpret_cast<hipStream_t>(stream), first, last);
+}
+
+fsp_status fsp_plan_get_schedule(fsp_plan p, int* variants) {
+  if (!p || !variants) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_get_schedule: NULL argument");
+  for (int i = 0; i < 5; ++i) variants[i] = p->var[i];
+  return FSP_OK;
+}
+
+fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants) {
+  if (!p || !variants) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: NULL argument");
+  for (int i = 0; i < 5; ++i)
+    if (variants[i] < 0 || variants[i] >= fsp::NUM_VARIANTS)
+      return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: variant out of range");
+  for (int i = 0; i < 5; ++i) p->var[i] = variants[i];
+  return FSP_OK;
+}
+
+fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* stream, float* times_ms) {
+  if (!p || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, "fsp_autotune: NULL argument");
+  if (!p->ready) return fail(FSP_ERR_NOT_READY, "fsp_autotune: plan has no bound buffers or no precomputed transform");
+  if (reps < 1 || reps > 8) return fail(FSP_ERR_INVALID_ARG, "fsp_autotune: reps must be in [1, 8]");
+  DeviceGuard guard;
+  hipError_t e = guard.enter(p->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_autotune: hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  int best[5];
+  for (int i = 0; i < 5; ++i) best[i] = p->var[i];
+  for (int pass = 0; pass < 5 && e == hipSuccess; ++pass) {
+    float best_ms = 1e30f;
+    for (int v = 0; v < fsp::NUM_VARIANTS && e == hipSuccess; ++v) {
+      // a full solve with the current best schedule puts valid data in the
+      // workspace; then one warm launch and `reps` timed launches of the pass
+      for (int i = 0; i < 5; ++i) p->var[i] = best[i];
+      fsp_status st = solve_one(p, rho, phi, s);
+      if (st != FSP_OK) {
+        e = hipErrorLaunchFailure;
+        break;
+      }
+      p->var[pass] = v;
+      st = solve_one(p, rho, phi, s, pass, pass);
+      if (st == FSP_OK) e = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && st == FSP_OK && e == hipSuccess; ++r) st = solve_one(p, rho, phi, s, pass, pass);
+      if (st != FSP_OK) {
+        e = hipErrorLaunchFailure;
+        break;
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      if (times_ms) times_ms[pass * fsp::NUM_VARIANTS + v] = ms;
+      if (e == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best[pass] = v;
+      }
+    }
+  }
+  for (int i = 0; i < 5; ++i) p->var[i] = best[i];
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail_hip(e, "fsp_autotune");
+  // leave a correct result in phi with the tuned schedule
+  fsp_status st = solve_one(p, rho, phi, s);
+  if (st != FSP_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::array<int, 5> a;
+    for (int i = 0; i < 5; ++i) a[i] = best[i];
+    g_tuned[TuneKey{p->n[0], p->n[1], p->n[2], p->d.prec}] = a;
+  }
+  return FSP_OK;
 }
 
 fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const* rho, void* const* phi,

@@ -33,8 +33,32 @@ struct RadixPlan {
   int r[4];
 };
 
-// Radix sequence for each supported pencil length (2^a or 3 * 2^a, 8..1024).
-__host__ __device__ constexpr RadixPlan radix_plan(int L) {
+// Radix sequences for each supported pencil length (2^a or 3 * 2^a, 8..1024).
+// Plan 0 is the default; plan 1 is an alternative (fewer, larger stages or
+// more, smaller ones) the autotuner may pick.  The first radix is always even.
+constexpr int NUM_PLANS = 2;
+
+__host__ __device__ constexpr RadixPlan radix_plan(int L, int pid = 0) {
+  if (pid == 1) {
+    switch (L) {
+      case 8: return {1, {8, 0, 0, 0}};
+      case 12: return {2, {4, 3, 0, 0}};
+      case 16: return {2, {4, 4, 0, 0}};
+      case 24: return {3, {2, 4, 3, 0}};
+      case 32: return {2, {16, 2, 0, 0}};
+      case 48: return {3, {4, 4, 3, 0}};
+      case 64: return {2, {16, 4, 0, 0}};
+      case 96: return {3, {16, 2, 3, 0}};
+      case 128: return {2, {8, 16, 0, 0}};
+      case 192: return {3, {16, 4, 3, 0}};
+      case 256: return {3, {8, 4, 8, 0}};
+      case 384: return {3, {8, 16, 3, 0}};
+      case 512: return {3, {8, 8, 8, 0}};
+      case 768: return {4, {16, 4, 4, 3}};
+      case 1024: return {3, {16, 8, 8, 0}};
+      default: return {0, {0, 0, 0, 0}};
+    }
+  }
   switch (L) {
     case 8: return {1, {8, 0, 0, 0}};
     case 12: return {2, {4, 3, 0, 0}};
@@ -55,16 +79,16 @@ __host__ __device__ constexpr RadixPlan radix_plan(int L) {
   }
 }
 
-__host__ __device__ constexpr int plan_len(int L) { return radix_plan(L).n; }
+__host__ __device__ constexpr int plan_len(int L, int pid = 0) { return radix_plan(L, pid).n; }
 
-// Radix of stage s; REV selects the reversed plan used by inverse transforms.
-__host__ __device__ constexpr int plan_radix(int L, bool rev, int s) {
-  return rev ? radix_plan(L).r[radix_plan(L).n - 1 - s] : radix_plan(L).r[s];
+// Radix of stage s; rev selects the reversed plan used by inverse transforms.
+__host__ __device__ constexpr int plan_radix(int L, int pid, bool rev, int s) {
+  return rev ? radix_plan(L, pid).r[radix_plan(L, pid).n - 1 - s] : radix_plan(L, pid).r[s];
 }
 
-__host__ __device__ constexpr int plan_ns(int L, bool rev, int s) {
+__host__ __device__ constexpr int plan_ns(int L, int pid, bool rev, int s) {
   int ns = 1;
-  for (int i = 0; i < s; ++i) ns *= plan_radix(L, rev, i);
+  for (int i = 0; i < s; ++i) ns *= plan_radix(L, pid, rev, i);
   return ns;
 }
 
@@ -75,19 +99,23 @@ __host__ __device__ constexpr int plan_ns(int L, bool rev, int s) {
 constexpr int TW_PER_K = 6;
 __host__ __device__ constexpr int tw_power(int e) { return e == 5 ? 3 : (1 << e); }
 
-__host__ __device__ constexpr int tw_stage_off(int L, bool rev, int s) {
+__host__ __device__ constexpr int tw_stage_off(int L, int pid, bool rev, int s) {
   int off = 0;
-  for (int i = 1; i < s; ++i) off += plan_ns(L, rev, i) * TW_PER_K;
+  for (int i = 1; i < s; ++i) off += plan_ns(L, pid, rev, i) * TW_PER_K;
   return off;
 }
 
-__host__ __device__ constexpr int tw_order_size(int L, bool rev) {
-  return tw_stage_off(L, rev, plan_len(L));
+__host__ __device__ constexpr int tw_order_size(int L, int pid, bool rev) {
+  return tw_stage_off(L, pid, rev, plan_len(L, pid));
 }
 
-// Table for a length: forward order, then reversed order.
-__host__ __device__ constexpr int tw_size(int L) { return tw_order_size(L, false) + tw_order_size(L, true); }
-__host__ __device__ constexpr int tw_base(int L, bool rev) { return rev ? tw_order_size(L, false) : 0; }
+// Table for one length and plan: forward order, then reversed order.
+__host__ __device__ constexpr int tw_size(int L, int pid) {
+  return tw_order_size(L, pid, false) + tw_order_size(L, pid, true);
+}
+__host__ __device__ constexpr int tw_base(int L, int pid, bool rev) {
+  return rev ? tw_order_size(L, pid, false) : 0;
+}
 
 // ---------------------------------------------------------------- complex
 template <typename T>
@@ -331,13 +359,13 @@ __device__ __forceinline__ void apply_twiddles(cx<T>* v, const cx<T>* __restrict
 
 // One middle stage: inputs from LDS, outputs back to LDS (in place, two barriers).
 // idx(row) maps a pencil row to this thread's LDS slot.
-template <typename T, int L, bool REV, int S, int NQ, bool INV, class IDX>
+template <typename T, int L, int PID, bool REV, int S, int NQ, bool INV, class IDX>
 __device__ __forceinline__ void lds_stage(cx<T>* lds, const cx<T>* __restrict__ tw, int q, IDX idx) {
-  constexpr int R = plan_radix(L, REV, S);
-  constexpr int NS = plan_ns(L, REV, S);
+  constexpr int R = plan_radix(L, PID, REV, S);
+  constexpr int NS = plan_ns(L, PID, REV, S);
   constexpr int NB = L / R;
   constexpr int J = (NB + NQ - 1) / NQ;
-  const cx<T>* tws = tw + tw_base(L, REV) + tw_stage_off(L, REV, S);
+  const cx<T>* tws = tw + tw_base(L, PID, REV) + tw_stage_off(L, PID, REV, S);
   cx<T> v[J][R];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -362,25 +390,25 @@ __device__ __forceinline__ void lds_stage(cx<T>* lds, const cx<T>* __restrict__ 
   lds_barrier();
 }
 
-template <typename T, int L, bool REV, int S, int SEND, int NQ, bool INV, class IDX>
+template <typename T, int L, int PID, bool REV, int S, int SEND, int NQ, bool INV, class IDX>
 __device__ __forceinline__ void lds_stages(cx<T>* lds, const cx<T>* __restrict__ tw, int q, IDX idx) {
   if constexpr (S < SEND) {
-    lds_stage<T, L, REV, S, NQ, INV>(lds, tw, q, idx);
-    lds_stages<T, L, REV, S + 1, SEND, NQ, INV>(lds, tw, q, idx);
+    lds_stage<T, L, PID, REV, S, NQ, INV>(lds, tw, q, idx);
+    lds_stages<T, L, PID, REV, S + 1, SEND, NQ, INV>(lds, tw, q, idx);
   }
 }
 
 // Last stage: inputs from LDS, outputs left in registers v[j][m] = row b + m L/R.
-template <typename T, int L, bool REV, int NQ, bool INV, int J, int R, class IDX>
+template <typename T, int L, int PID, bool REV, int NQ, bool INV, int J, int R, class IDX>
 __device__ __forceinline__ void lds_last_stage(const cx<T>* lds, const cx<T>* __restrict__ tw, int q,
                                                IDX idx, cx<T> (&v)[J][R]) {
-  constexpr int S = plan_len(L) - 1;
-  constexpr int NS = plan_ns(L, REV, S);
+  constexpr int S = plan_len(L, PID) - 1;
+  constexpr int NS = plan_ns(L, PID, REV, S);
   constexpr int NB = L / R;
-  static_assert(R == plan_radix(L, REV, S), "register array matches the last radix");
+  static_assert(R == plan_radix(L, PID, REV, S), "register array matches the last radix");
   static_assert(J == (NB + NQ - 1) / NQ, "register array matches the butterfly split");
   static_assert(NS == NB, "last stage spans the pencil");
-  const cx<T>* tws = tw + tw_base(L, REV) + tw_stage_off(L, REV, S);
+  const cx<T>* tws = tw + tw_base(L, PID, REV) + tw_stage_off(L, PID, REV, S);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int b = q + NQ * j;
@@ -407,15 +435,15 @@ __device__ __forceinline__ void write_first_outputs(cx<T>* lds, const cx<T> (&v)
 }
 
 // Shape helpers for register arrays of the first / last stage.
-template <int L, bool REV, int NQ>
+template <int L, int PID, bool REV, int NQ>
 struct FirstStage {
-  static constexpr int R = plan_radix(L, REV, 0);
+  static constexpr int R = plan_radix(L, PID, REV, 0);
   static constexpr int NB = L / R;
   static constexpr int J = (NB + NQ - 1) / NQ;
 };
-template <int L, bool REV, int NQ>
+template <int L, int PID, bool REV, int NQ>
 struct LastStage {
-  static constexpr int R = plan_radix(L, REV, plan_len(L) - 1);
+  static constexpr int R = plan_radix(L, PID, REV, plan_len(L, PID) - 1);
   static constexpr int NB = L / R;
   static constexpr int J = (NB + NQ - 1) / NQ;
 };

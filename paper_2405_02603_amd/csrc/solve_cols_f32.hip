@@ -1,0 +1,6 @@
+// Column-pass launchers (float): every length and schedule variant of P2, P3 and P4.
+#include "solve_launch.hpp"
+
+namespace fsp {
+template hipError_t launch_col<float>(int, int, int, const ColArgs&, int, hipStream_t);
+}  // namespace fsp

@@ -79,9 +79,9 @@ __device__ __forceinline__ void place_column(const ColArgs& a, int c, int& col, 
 }
 
 // ----------------------------------------------------------------- P2 / P4
-template <typename T, int L, int TC, int NQ, bool INV>
+template <typename T, int L, int PID, int TC, int NQ, bool INV>
 __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
-  constexpr int K = plan_len(L);
+  constexpr int K = plan_len(L, PID);
   __shared__ cx<T> lds[K > 1 ? L * TC : 1];
   const int tid = threadIdx.x;
   const int c = tid % TC, q = tid / TC;
@@ -93,7 +93,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
   const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
   auto idx = [c](int row) { return row * TC + c; };
   constexpr bool REV = INV;
-  using F = FirstStage<L, REV, NQ>;
+  using F = FirstStage<L, PID, REV, NQ>;
   static_assert(INV || F::R % 2 == 0, "forward plans start with an even radix");
 
   cx<T> v[F::J][F::R];
@@ -122,11 +122,11 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
   } else {
     write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
     lds_barrier();
-    lds_stages<T, L, REV, 1, K - 1, NQ, INV>(lds, tw, q, idx);
-    using Ls = LastStage<L, REV, NQ>;
+    lds_stages<T, L, PID, REV, 1, K - 1, NQ, INV>(lds, tw, q, idx);
+    using Ls = LastStage<L, PID, REV, NQ>;
     static_assert(!INV || Ls::R % 2 == 0, "inverse plans end with an even radix");
     cx<T> w[Ls::J][Ls::R];
-    lds_last_stage<T, L, REV, NQ, INV>(lds, tw, q, idx, w);
+    lds_last_stage<T, L, PID, REV, NQ, INV>(lds, tw, q, idx, w);
 #pragma unroll
     for (int j = 0; j < Ls::J; ++j) {
       const int b = q + NQ * j;
@@ -140,9 +140,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
 }
 
 // ----------------------------------------------------------------- P3
-template <typename T, int L, int TC, int NQ>
+template <typename T, int L, int PID, int TC, int NQ>
 __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
-  constexpr int K = plan_len(L);
+  constexpr int K = plan_len(L, PID);
   __shared__ cx<T> lds[K > 1 ? L * TC : 1];
   const int tid = threadIdx.x;
   const int c = tid % TC, q = tid / TC;
@@ -152,8 +152,8 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
   auto idx = [c](int row) { return row * TC + c; };
-  using F = FirstStage<L, false, NQ>;   // forward, first stage
-  using Lf = LastStage<L, false, NQ>;   // forward, last stage == inverse, first stage
+  using F = FirstStage<L, PID, false, NQ>;   // forward, first stage
+  using Lf = LastStage<L, PID, false, NQ>;   // forward, last stage == inverse, first stage
   static_assert(F::R % 2 == 0, "forward plans start with an even radix");
 
   // Green's values for the rows this thread holds after the forward transform;
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   // k1 = p and its partner 2 n1 - p share the Green's rows; p = 0 and p = n1
   // have no partner.  Both pencil sets are loaded before either is
   // transformed, so the second set's loads overlap the first set's work.
-  using Li = LastStage<L, true, NQ>;
+  using Li = LastStage<L, PID, true, NQ>;
   static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
   const bool two = !(p == 0 || p == a.n1);
   cx<T>* base_a = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)p * a.outer_stride + col;
@@ -214,9 +214,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
     } else {
       write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
       lds_barrier();
-      lds_stages<T, L, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
+      lds_stages<T, L, PID, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
       cx<T> w[Lf::J][Lf::R];
-      lds_last_stage<T, L, false, NQ, false>(lds, tw, q, idx, w);
+      lds_last_stage<T, L, PID, false, NQ, false>(lds, tw, q, idx, w);
       // multiply, then the first inverse stage (span 1) in registers
 #pragma unroll
       for (int j = 0; j < Lf::J; ++j) {
@@ -227,9 +227,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       lds_barrier();
       write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, w, q, idx);
       lds_barrier();
-      lds_stages<T, L, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
+      lds_stages<T, L, PID, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
       cx<T> u[Li::J][Li::R];
-      lds_last_stage<T, L, true, NQ, true>(lds, tw, q, idx, u);
+      lds_last_stage<T, L, PID, true, NQ, true>(lds, tw, q, idx, u);
 #pragma unroll
       for (int j = 0; j < Li::J; ++j) {
         const int b = q + NQ * j;
@@ -254,9 +254,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
 // Row of n2 = LC reals x (zero-padded to 2 LC): z[n] = x[2n] + i x[2n+1]
 // (n < LC/2, zero above), Z = DFT_LC(z), then for k in [0, LC]
 //   X[k] = (Z[k] + conj Z[LC-k]) / 2 - i e^{-i pi k / LC} (Z[k] - conj Z[LC-k]) / 2.
-template <typename T, int LC, int TR, int NQ>
+template <typename T, int LC, int PID, int TR, int NQ>
 __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
-  constexpr int K = plan_len(LC);
+  constexpr int K = plan_len(LC, PID);
   constexpr int LP = row_pitch(LC);
   __shared__ cx<T> lds[TR * LP];
   const int tid = threadIdx.x;
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
   const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in[blockIdx.y]) + (long long)row * (LC / 2);
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   auto idx = [c](int e) { return c * LP + row_slot(e); };
-  using F = FirstStage<LC, false, NQ>;
+  using F = FirstStage<LC, PID, false, NQ>;
   static_assert(F::R % 2 == 0, "forward plans start with an even radix");
 
   cx<T> v[F::J][F::R];
@@ -283,10 +283,10 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
   } else {
     write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
     lds_barrier();
-    lds_stages<T, LC, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
-    using Ls = LastStage<LC, false, NQ>;
+    lds_stages<T, LC, PID, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
+    using Ls = LastStage<LC, PID, false, NQ>;
     cx<T> w[Ls::J][Ls::R];
-    lds_last_stage<T, LC, false, NQ, false>(lds, tw, q, idx, w);
+    lds_last_stage<T, LC, PID, false, NQ, false>(lds, tw, q, idx, w);
     lds_barrier();
 #pragma unroll
     for (int j = 0; j < Ls::J; ++j) {
@@ -299,7 +299,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
   }
   lds_barrier();
   if (!rok) return;
-  const cx<T>* pp = tw + tw_size(LC);
+  const cx<T>* pp = tw + tw_size(LC, PID);
   const int i0 = row / a.n1, i1 = row - i0 * a.n1;
   cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
   constexpr int JO = (LC + 1 + NQ - 1) / NQ;
@@ -321,9 +321,9 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
 // From X[k], k in [0, LC] (half spectrum of a real row of length 2 LC):
 //   Y[n] = (X[n] + conj X[LC-n]) + i e^{+i pi n / LC} (X[n] - conj X[LC-n]),
 //   z = inverse DFT_LC(Y), x[2n] = Re z[n], x[2n+1] = Im z[n]; keep n < LC/2.
-template <typename T, int LC, int TR, int NQ>
+template <typename T, int LC, int PID, int TR, int NQ>
 __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
-  constexpr int K = plan_len(LC);
+  constexpr int K = plan_len(LC, PID);
   constexpr int LP = row_pitch(LC);
   __shared__ cx<T> lds[TR * LP];
   const int tid = threadIdx.x;
@@ -344,8 +344,8 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
     }
   }
   lds_barrier();
-  const cx<T>* pp = tw + tw_size(LC);
-  using F = FirstStage<LC, true, NQ>;
+  const cx<T>* pp = tw + tw_size(LC, PID);
+  using F = FirstStage<LC, PID, true, NQ>;
   cx<T> v[F::J][F::R];
 #pragma unroll
   for (int j = 0; j < F::J; ++j) {
@@ -380,11 +380,11 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
     lds_barrier();
     write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
     lds_barrier();
-    lds_stages<T, LC, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
-    using Li = LastStage<LC, true, NQ>;
+    lds_stages<T, LC, PID, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
+    using Li = LastStage<LC, PID, true, NQ>;
     static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
     cx<T> u[Li::J][Li::R];
-    lds_last_stage<T, LC, true, NQ, true>(lds, tw, q, idx, u);
+    lds_last_stage<T, LC, PID, true, NQ, true>(lds, tw, q, idx, u);
     if (rok) {
 #pragma unroll
       for (int j = 0; j < Li::J; ++j) {

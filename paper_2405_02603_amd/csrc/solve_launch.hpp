@@ -7,126 +7,154 @@
 namespace fsp {
 
 struct TileCfg {
+  int pid;    // radix plan (fft_core.hpp)
   int tiles;  // TC (column passes: columns per block) or TR (row passes: rows per block)
   int nq;     // threads per pencil
 };
 
-// Column passes (pencil length L = 2 n, strided rows).  LDS = L * TC * sizeof(cx<T>).
+// Schedule variants per pencil length; variant 0 is the default and the
+// autotuner may pick another.  Column passes of one length share TC (the
+// Green's octant is stored in tiles of the axis-0 pass's TC).
+constexpr int NUM_VARIANTS = 3;
+
 template <typename T>
-__host__ __device__ constexpr TileCfg col_cfg(int L) {
+__host__ __device__ constexpr int col_tc(int L) {
   constexpr bool d = sizeof(T) == 8;
   switch (L) {
-    case 16: return {d ? 32 : 64, 1};
-    case 24: return {d ? 32 : 64, 1};
-    case 32: return {32, 4};
-    case 48: return {d ? 32 : 64, 1};
-    case 64: return {d ? 16 : 32, 8};
-    case 96: return {d ? 16 : 32, 4};
-    case 128: return {d ? 16 : 32, 8};
-    case 192: return {d ? 8 : 16, 8};
-    case 256: return {d ? 8 : 16, 16};
-    case 384: return {d ? 8 : 16, 8};
-    case 512: return {d ? 8 : 16, 16};
-    case 768: return {d ? 4 : 8, 16};
-    case 1024: return {d ? 4 : 8, 32};
-    default: return {0, 0};
+    case 16: case 24: case 48: return d ? 32 : 64;
+    case 32: return 32;
+    case 64: case 96: case 128: return d ? 16 : 32;
+    case 192: case 256: case 384: case 512: return d ? 8 : 16;
+    case 768: case 1024: return d ? 4 : 8;
+    default: return 0;
+  }
+}
+
+// Column passes (pencil length L = 2 n, strided rows).  LDS = L * TC * sizeof(cx<T>).
+template <typename T>
+__host__ __device__ constexpr TileCfg col_cfg(int L, int v) {
+  const int tc = col_tc<T>(L);
+  switch (L) {
+    case 16: return v == 0 ? TileCfg{0, tc, 1} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{1, tc, 2};
+    case 24: return v == 0 ? TileCfg{0, tc, 1} : v == 1 ? TileCfg{1, tc, 2} : TileCfg{0, tc, 3};
+    case 32: return v == 0 ? TileCfg{0, tc, 4} : v == 1 ? TileCfg{1, tc, 2} : TileCfg{0, tc, 8};
+    case 48: return v == 0 ? TileCfg{0, tc, 1} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{0, tc, 3};
+    case 64: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{0, tc, 4};
+    case 96: return v == 0 ? TileCfg{0, tc, 4} : v == 1 ? TileCfg{1, tc, 2} : TileCfg{0, tc, 8};
+    case 128: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 8} : TileCfg{0, tc, 16};
+    case 192: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{0, tc, 16};
+    case 256: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tc, 8};
+    case 384: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 8} : TileCfg{0, tc, 16};
+    case 512: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{1, tc, 16};
+    case 768: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 16} : TileCfg{0, tc, 32};
+    case 1024: return v == 0 ? TileCfg{0, tc, 32} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tc, 16};
+    default: return {0, 0, 0};
   }
 }
 
 // Row passes (pencil length LC = n2 complex, contiguous rows).  LDS = TR row_pitch(LC) sizeof(cx<T>).
 template <typename T>
-__host__ __device__ constexpr TileCfg row_cfg(int LC) {
+__host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
   constexpr bool d = sizeof(T) == 8;
   switch (LC) {
-    case 8: return {64, 1};
-    case 12: return {64, 1};
-    case 16: return {64, 1};
-    case 24: return {64, 1};
-    case 32: return {32, 4};
-    case 48: return {d ? 32 : 64, 1};
-    case 64: return {32, 8};
-    case 96: return {32, 4};
-    case 128: return {d ? 8 : 16, 8};
-    case 192: return {d ? 8 : 16, 8};
-    case 256: return {d ? 8 : 16, 16};
-    case 384: return {d ? 4 : 8, 8};
-    case 512: return {d ? 4 : 8, 16};
-    default: return {0, 0};
+    case 8: return v == 0 ? TileCfg{0, 64, 1} : v == 1 ? TileCfg{0, 32, 1} : TileCfg{0, 16, 1};
+    case 12: return v == 0 ? TileCfg{0, 64, 1} : v == 1 ? TileCfg{0, 32, 1} : TileCfg{0, 64, 3};
+    case 16: return v == 0 ? TileCfg{0, 64, 1} : v == 1 ? TileCfg{1, 32, 4} : TileCfg{1, 64, 2};
+    case 24: return v == 0 ? TileCfg{0, 64, 1} : v == 1 ? TileCfg{1, 32, 2} : TileCfg{0, 32, 3};
+    case 32: return v == 0 ? TileCfg{0, 32, 4} : v == 1 ? TileCfg{1, 32, 2} : TileCfg{0, 16, 8};
+    case 48: return v == 0 ? TileCfg{0, d ? 32 : 64, 1} : v == 1 ? TileCfg{1, 32, 4} : TileCfg{0, 32, 3};
+    case 64: return v == 0 ? TileCfg{0, 32, 8} : v == 1 ? TileCfg{1, 32, 4} : TileCfg{0, 16, 8};
+    case 96: return v == 0 ? TileCfg{0, 32, 4} : v == 1 ? TileCfg{1, 32, 2} : TileCfg{0, 16, 8};
+    case 128: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 8} : TileCfg{0, 32, 8};
+    case 192: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 4} : TileCfg{0, 8, 16};
+    case 256: return v == 0 ? TileCfg{0, d ? 8 : 16, 16} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{0, d ? 4 : 8, 16};
+    case 384: return v == 0 ? TileCfg{0, d ? 4 : 8, 8} : v == 1 ? TileCfg{1, 8, 8} : TileCfg{0, 4, 16};
+    case 512: return v == 0 ? TileCfg{0, d ? 4 : 8, 16} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{0, d ? 8 : 16, 16};
+    default: return {0, 0, 0};
   }
 }
 
 #define FSP_ROW_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
 #define FSP_COL_LENGTHS(X) \
   X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+#define FSP_VARIANTS(X, LV) X(LV, 0) X(LV, 1) X(LV, 2)
 
 template <typename T>
-hipError_t launch_p1(int LC, const RowArgs& a, int items, hipStream_t s) {
-  switch (LC) {
-#define FSP_CASE(LV)                                                                        \
-  case LV: {                                                                                \
-    constexpr TileCfg c = row_cfg<T>(LV);                                                   \
-    const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                   \
-    hipLaunchKernelGGL((k_row_r2c<T, LV, c.tiles, c.nq>), dim3(blocks, items), dim3(c.tiles * c.nq), 0, s, a); \
-    break;                                                                                  \
+hipError_t launch_p1(int LC, int v, const RowArgs& a, int items, hipStream_t s) {
+  bool found = false;
+#define FSP_CASE_V(LV, VV)                                                                          \
+  if (LC == LV && v == VV) {                                                                        \
+    constexpr TileCfg c = row_cfg<T>(LV, VV);                                                       \
+    const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                           \
+    hipLaunchKernelGGL((k_row_r2c<T, LV, c.pid, c.tiles, c.nq>), dim3(blocks, items), dim3(c.tiles * c.nq), 0, s, a); \
+    found = true;                                                                                   \
   }
-    FSP_ROW_LENGTHS(FSP_CASE)
+#define FSP_CASE(LV) FSP_VARIANTS(FSP_CASE_V, LV)
+  FSP_ROW_LENGTHS(FSP_CASE)
 #undef FSP_CASE
-    default: return hipErrorInvalidValue;
-  }
+#undef FSP_CASE_V
+  if (!found) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_p5(int LC, const RowArgs& a, int items, hipStream_t s) {
-  switch (LC) {
-#define FSP_CASE(LV)                                                                        \
-  case LV: {                                                                                \
-    constexpr TileCfg c = row_cfg<T>(LV);                                                   \
-    const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                   \
-    hipLaunchKernelGGL((k_row_c2r<T, LV, c.tiles, c.nq>), dim3(blocks, items), dim3(c.tiles * c.nq), 0, s, a); \
-    break;                                                                                  \
+hipError_t launch_p5(int LC, int v, const RowArgs& a, int items, hipStream_t s) {
+  bool found = false;
+#define FSP_CASE_V(LV, VV)                                                                          \
+  if (LC == LV && v == VV) {                                                                        \
+    constexpr TileCfg c = row_cfg<T>(LV, VV);                                                       \
+    const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                           \
+    hipLaunchKernelGGL((k_row_c2r<T, LV, c.pid, c.tiles, c.nq>), dim3(blocks, items), dim3(c.tiles * c.nq), 0, s, a); \
+    found = true;                                                                                   \
   }
-    FSP_ROW_LENGTHS(FSP_CASE)
+#define FSP_CASE(LV) FSP_VARIANTS(FSP_CASE_V, LV)
+  FSP_ROW_LENGTHS(FSP_CASE)
 #undef FSP_CASE
-    default: return hipErrorInvalidValue;
-  }
+#undef FSP_CASE_V
+  if (!found) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 template <typename T>
 int col_tiles(int L) {
-  switch (L) {
-#define FSP_CASE(LV) \
-  case LV: return col_cfg<T>(LV).tiles;
-    FSP_COL_LENGTHS(FSP_CASE)
-#undef FSP_CASE
-    default: return 0;
-  }
+  return col_tc<T>(L);
 }
 
-// nouter: outer pencils groups (P2/P4: n0; P3: n1 + 1 pairs)
+// kind: 0 forward (P2), 1 inverse (P4), 2 forward-multiply-inverse (P3)
 template <typename T>
-hipError_t launch_col(int L, bool inverse, bool conv, const ColArgs& a, int items, hipStream_t s) {
-  switch (L) {
-#define FSP_CASE(LV)                                                                              \
-  case LV: {                                                                                      \
-    constexpr TileCfg c = col_cfg<T>(LV);                                                         \
-    const dim3 grid((unsigned)(a.nouter * a.ntiles), (unsigned)items);                            \
-    const dim3 block(c.tiles * c.nq);                                                             \
-    if (conv)                                                                                     \
-      hipLaunchKernelGGL((k_col_conv<T, LV, c.tiles, c.nq>), grid, block, 0, s, a);               \
-    else if (inverse)                                                                             \
-      hipLaunchKernelGGL((k_col_fft<T, LV, c.tiles, c.nq, true>), grid, block, 0, s, a);          \
-    else                                                                                          \
-      hipLaunchKernelGGL((k_col_fft<T, LV, c.tiles, c.nq, false>), grid, block, 0, s, a);         \
-    break;                                                                                        \
+hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipStream_t s) {
+  bool found = false;
+#define FSP_CASE_V(LV, VV)                                                                          \
+  if (L == LV && v == VV) {                                                                         \
+    constexpr TileCfg c = col_cfg<T>(LV, VV);                                                       \
+    const dim3 grid((unsigned)(a.nouter * a.ntiles), (unsigned)items);                              \
+    const dim3 block(c.tiles * c.nq);                                                               \
+    if (kind == 2)                                                                                  \
+      hipLaunchKernelGGL((k_col_conv<T, LV, c.pid, c.tiles, c.nq>), grid, block, 0, s, a);          \
+    else if (kind == 1)                                                                             \
+      hipLaunchKernelGGL((k_col_fft<T, LV, c.pid, c.tiles, c.nq, true>), grid, block, 0, s, a);     \
+    else                                                                                            \
+      hipLaunchKernelGGL((k_col_fft<T, LV, c.pid, c.tiles, c.nq, false>), grid, block, 0, s, a);    \
+    found = true;                                                                                   \
   }
-    FSP_COL_LENGTHS(FSP_CASE)
+#define FSP_CASE(LV) FSP_VARIANTS(FSP_CASE_V, LV)
+  FSP_COL_LENGTHS(FSP_CASE)
 #undef FSP_CASE
-    default: return hipErrorInvalidValue;
-  }
+#undef FSP_CASE_V
+  if (!found) return hipErrorInvalidValue;
   return hipGetLastError();
 }
+
+#ifdef FSP_SPLIT_LAUNCHERS
+// The launchers are instantiated in their own translation units (compiled in
+// parallel); the solve driver only references them.
+extern template hipError_t launch_p1<float>(int, int, const RowArgs&, int, hipStream_t);
+extern template hipError_t launch_p5<float>(int, int, const RowArgs&, int, hipStream_t);
+extern template hipError_t launch_col<float>(int, int, int, const ColArgs&, int, hipStream_t);
+extern template hipError_t launch_p1<double>(int, int, const RowArgs&, int, hipStream_t);
+extern template hipError_t launch_p5<double>(int, int, const RowArgs&, int, hipStream_t);
+extern template hipError_t launch_col<double>(int, int, int, const ColArgs&, int, hipStream_t);
+#endif
 
 // Geometry of up to MAX_ITEMS solves of one shape, filled by the plans.
 struct SolveGeom {
@@ -135,9 +163,10 @@ struct SolveGeom {
   int pitch;                 // P
   long long plane;           // complex elements between S planes i0 (>= 2 n1 P)
   int chunks;                // column chunks for passes 1-3 (1: whole passes)
-  const void* tw_row;        // twiddles, length n2 (+ split table)
-  const void* tw_c1;         // twiddles, length 2 n1
-  const void* tw_c0;         // twiddles, length 2 n0
+  int var[5];                // schedule variant of each pass
+  const void* tw_row[5];     // twiddles of length n2 (+ split table) for the plan of P1 / P5
+  const void* tw_c1[5];      // twiddles of length 2 n1 for the plan of P2 / P4
+  const void* tw_c0;         // twiddles of length 2 n0 for the plan of P3
   const void* ghat[MAX_ITEMS];  // octant of each item, blocked [n1+1][tiles][n0+1][TC of P3]
   void* work[MAX_ITEMS];        // S of each item
   const void* rho[MAX_ITEMS];
@@ -154,7 +183,7 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
   ra.n1 = g.n1;
   ra.pitch = g.pitch;
   ra.s_i0_stride = plane;
-  ra.tw = g.tw_row;
+
   // P2 / P4: pencils along axis 1; outer = i0
   ColArgs ca{};
   for (int i = 0; i < g.items; ++i) ca.data[i] = g.work[i];
@@ -162,7 +191,7 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
   ca.row_stride = P;
   ca.outer_stride = plane;
   ca.nouter = g.n0;
-  ca.tw = g.tw_c1;
+
   // P3: pencils along axis 0; outer = k1 pairs
   ColArgs cc{};
   for (int i = 0; i < g.items; ++i) {
@@ -193,16 +222,24 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
           ra.in[i] = g.rho[i];
           ra.out[i] = g.work[i];
         }
-        return launch_p1<T>(g.n2, ra, g.items, s);
-      case 1: set_cols(ca, tc1, c0, c1); return launch_col<T>(2 * g.n1, false, false, ca, g.items, s);
-      case 2: set_cols(cc, tc0, c0, c1); return launch_col<T>(2 * g.n0, false, true, cc, g.items, s);
-      case 3: set_cols(ca, tc1, c0, c1); return launch_col<T>(2 * g.n1, true, false, ca, g.items, s);
+        ra.tw = g.tw_row[0];
+        return launch_p1<T>(g.n2, g.var[0], ra, g.items, s);
+      case 1:
+        set_cols(ca, tc1, c0, c1);
+        ca.tw = g.tw_c1[1];
+        return launch_col<T>(2 * g.n1, g.var[1], 0, ca, g.items, s);
+      case 2: set_cols(cc, tc0, c0, c1); return launch_col<T>(2 * g.n0, g.var[2], 2, cc, g.items, s);
+      case 3:
+        set_cols(ca, tc1, c0, c1);
+        ca.tw = g.tw_c1[3];
+        return launch_col<T>(2 * g.n1, g.var[3], 1, ca, g.items, s);
       case 4:
         for (int i = 0; i < g.items; ++i) {
           ra.in[i] = g.work[i];
           ra.out[i] = g.phi[i];
         }
-        return launch_p5<T>(g.n2, ra, g.items, s);
+        ra.tw = g.tw_row[4];
+        return launch_p5<T>(g.n2, g.var[4], ra, g.items, s);
       default: return hipErrorInvalidValue;
     }
   };

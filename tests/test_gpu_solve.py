@@ -111,3 +111,51 @@ def test_in_place(torch_cuda):
     plan.solve(t, out=t)
     torch.cuda.synchronize()
     assert rel_l2(to_host(t), reference(rho, "vico_dct", lo, hi, use_direct=False)) <= F64_TOL
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 96, 128, (64, 96, 48)])
+def test_every_schedule_variant(torch_cuda, prec, tol, n):
+    """Every kernel variant the autotuner may pick gives the oracle's result."""
+    from paper_2405_02603_amd import _lib
+    torch = torch_cuda
+    n3 = W._as3(n, int)
+    lo, hi = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+    rho = W.random_field(n3, 13)
+    ref = reference(rho, "vico_dct", lo, hi, use_direct=max(n3) <= 16)
+    plan = _plan(n3, lo, hi, "vico_dct", prec)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    r = to_dev(rho, dt)
+    for v in range(_lib.NUM_VARIANTS):
+        plan.schedule = [v] * 5
+        phi = plan.solve(r)
+        torch.cuda.synchronize()
+        assert rel_l2(to_host(phi), ref) <= tol, f"variant {v}"
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_autotune_256(torch_cuda, prec):
+    """The autotuner at the benchmark size: timings for every variant, and the tuned
+    schedule still matches the oracle."""
+    torch = torch_cuda
+    n, lo, hi = 256, (-1.0,) * 3, (1.0,) * 3
+    rho = W.source_density(n, lo, hi, W.multiblob(3))
+    plan = _plan(n, lo, hi, "vico_dct", prec)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    r = to_dev(rho, dt)
+    times = plan.autotune(r, reps=2)
+    torch.cuda.synchronize()
+    assert all(t > 0 for ts in times.values() for t in ts)
+    sched = plan.schedule
+    for p in range(5):
+        assert times[p][sched[p]] == min(times[p])
+    phi = plan.solve(r)
+    torch.cuda.synchronize()
+    ref = reference(rho, "vico_dct", lo, hi, use_direct=False)
+    assert rel_l2(to_host(phi), ref) <= (F64_TOL if prec == "f64" else F32_TOL)
+    for v in range(3):
+        plan.schedule = [v] * 5
+        phi = plan.solve(r)
+        torch.cuda.synchronize()
+        assert rel_l2(to_host(phi), ref) <= (F64_TOL if prec == "f64" else F32_TOL), f"variant {v}"
+    print("autotune", prec, sched, {p: [round(t, 4) for t in ts] for p, ts in times.items()})
