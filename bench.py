@@ -302,7 +302,8 @@ def main(argv=None):
             "phi": phi.double().cpu().numpy(),
             "rb": 4 if prec == "f32" else 8,
             "schedule": plan.schedule,
-            "tune_ms": None if tune is None else {str(k): [round(x, 5) for x in v] for k, v in tune.items()},
+            "tune_ms": None if tune is None else {str(k): ([round(x, 5) for x in v] if isinstance(v, list) else round(v, 5))
+                                                  for k, v in tune.items()},
         }
         del plan, rho, phi
         torch.cuda.empty_cache()

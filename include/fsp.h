@@ -133,19 +133,26 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
 
 /* Schedules.  Every pass has NUM_VARIANTS = 3 kernel variants (radix plan,
  * threads per pencil, tile); variants[i] selects the one for pass i (0..4,
- * as in fsp_solve_passes).  Results are identical up to rounding order across
- * variants.  A new plan starts with the schedule last tuned for its grid and
+ * as in fsp_solve_passes).  The value 3 in variants[1..3] (all three) selects
+ * the fused schedule for small grids with n0 == n1 (n <= 64 in float32, <= 48
+ * in float64): one kernel holds a column tile's whole (axis 0, axis 1) slab in
+ * LDS and runs passes 1-3 there; fsp_solve_passes then accepts only ranges
+ * that contain all of 1-3.  Results are identical up to rounding order across
+ * schedules.  A new plan starts with the schedule last tuned for its grid and
  * precision in this process (else all zeros). */
 fsp_status fsp_plan_get_schedule(fsp_plan p, int* variants /* [5] */);
 fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants /* [5] */);
 
 /* Time every variant of every pass on this plan's buffers with HIP events
- * (reps timed launches each, 1 <= reps <= 8, after a warm launch), keep the
+ * placed around that pass inside full solves (reps timed solves per variant,
+ * 1 <= reps <= 8, after a warm one), keep the
  * fastest per pass in the plan and in the process-wide table used by new
  * plans of this grid and precision.  rho and phi are as in fsp_solve; on
  * return phi holds the solve of rho with the tuned schedule.  Synchronises
- * `stream`.  times_ms (NULL or [5 * 3]) receives the average time of each
- * variant: times_ms[pass * 3 + variant]. */
+ * `stream`.  times_ms (NULL or [5 * 3 + 2]) receives the average time of each
+ * variant, times_ms[pass * 3 + variant], then the time of passes 1-3 fused and
+ * of passes 1-3 with the best separate variants (0 when fusion is not
+ * supported); the fused schedule is kept when it is faster. */
 fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* stream, float* times_ms);
 
 /* count independent solves (each with its own plan, and so its own

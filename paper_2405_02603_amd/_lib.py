@@ -7,6 +7,7 @@ from __future__ import annotations
 import ctypes
 import os
 from ctypes import POINTER, c_char_p, c_double, c_int, c_size_t, c_uint, c_void_p
+from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfsp.so")
@@ -21,6 +22,7 @@ FSP_ERR_DEVICE = 6
 
 GREENS = {"hockney": 0, "vico": 1, "vico_dct": 2}
 NUM_VARIANTS = 3
+FUSED = 3  # schedule value of passes 1-3 selecting the fused small-grid kernel
 PREC = {"f32": 0, "f64": 1}
 
 # every symbol include/fsp.h declares
@@ -55,11 +57,15 @@ class FspError(RuntimeError):
 _lib = None
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load libfsp.so (built by ``python -m paper_2405_02603_amd.build``)."""
+def load(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load libfsp.so (built by ``python -m paper_2405_02603_amd.build``).
+
+    ``FSP_LIBRARY`` names another build of the same library to load instead.
+    """
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("FSP_LIBRARY") or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"libfsp.so not found at {path}; build it with "
                           "`python -m paper_2405_02603_amd.build` (hipcc, gfx950)")

@@ -533,8 +533,10 @@ static fsp::SolveGeom group_geom(const fsp_plan_s* p) {
   const char* gb = static_cast<const char*>(p->ghat_read);
   for (int i = 0; i < 5; ++i) g.var[i] = p->var[i];
   const int pr1 = fsp::row_cfg<float>(p->n[2], p->var[0]).pid, pr5 = fsp::row_cfg<float>(p->n[2], p->var[4]).pid;
-  const int pc2 = fsp::col_cfg<float>(2 * p->n[1], p->var[1]).pid, pc4 = fsp::col_cfg<float>(2 * p->n[1], p->var[3]).pid;
-  const int pc3 = fsp::col_cfg<float>(2 * p->n[0], p->var[2]).pid;
+  const bool fused = p->var[1] == fsp::FUSED;
+  const int pc2 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], p->var[1]).pid;
+  const int pc4 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], p->var[3]).pid;
+  const int pc3 = fused ? 0 : fsp::conv_cfg<float>(2 * p->n[0], p->var[2]).pid;
   for (int i = 0; i < 5; ++i) g.tw_row[i] = g.tw_c1[i] = nullptr;
   g.tw_row[0] = gb + p->tw_row_off[pr1];
   g.tw_row[4] = gb + p->tw_row_off[pr5];
@@ -643,11 +645,25 @@ fsp_status fsp_plan_get_schedule(fsp_plan p, int* variants) {
   return FSP_OK;
 }
 
+static bool fused_supported(const fsp_plan_s* p) {
+  if (p->n[0] != p->n[1] || p->chunks != 1) return false;
+  return p->d.prec == FSP_F64 ? fsp::slab_cfg<double>(2 * p->n[1]).tiles > 0
+                              : fsp::slab_cfg<float>(2 * p->n[1]).tiles > 0;
+}
+
 fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants) {
   if (!p || !variants) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: NULL argument");
-  for (int i = 0; i < 5; ++i)
-    if (variants[i] < 0 || variants[i] >= fsp::NUM_VARIANTS)
+  const bool fused = variants[1] == fsp::FUSED;
+  if (fused && (variants[2] != fsp::FUSED || variants[3] != fsp::FUSED || !fused_supported(p)))
+    return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: the fused schedule needs passes 1-3 all set to 3, "
+                                     "n0 == n1 and a grid small enough for the slab to fit in LDS");
+  for (int i = 0; i < 5; ++i) {
+    const bool mid = i >= 1 && i <= 3;
+    if (variants[i] < 0 || (variants[i] >= fsp::NUM_VARIANTS && !(mid && fused)))
       return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: variant out of range");
+    if (mid && !fused && variants[i] == fsp::FUSED)
+      return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: variant out of range");
+  }
   for (int i = 0; i < 5; ++i) p->var[i] = variants[i];
   return FSP_OK;
 }
@@ -665,36 +681,67 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
   if (e == hipSuccess) e = hipEventCreate(&e1);
   int best[5];
   for (int i = 0; i < 5; ++i) best[i] = p->var[i];
+  if (best[1] == fsp::FUSED) best[1] = best[2] = best[3] = 0;  // tune the separate passes first
+  // Each variant is timed inside full solves (the pass reads what the pass
+  // before it just wrote, as in a real solve): events around the pass only.
   for (int pass = 0; pass < 5 && e == hipSuccess; ++pass) {
     float best_ms = 1e30f;
     for (int v = 0; v < fsp::NUM_VARIANTS && e == hipSuccess; ++v) {
-      // a full solve with the current best schedule puts valid data in the
-      // workspace; then one warm launch and `reps` timed launches of the pass
       for (int i = 0; i < 5; ++i) p->var[i] = best[i];
-      fsp_status st = solve_one(p, rho, phi, s);
-      if (st != FSP_OK) {
-        e = hipErrorLaunchFailure;
-        break;
-      }
       p->var[pass] = v;
-      st = solve_one(p, rho, phi, s, pass, pass);
-      if (st == FSP_OK) e = hipEventRecord(e0, s);
-      for (int r = 0; r < reps && st == FSP_OK && e == hipSuccess; ++r) st = solve_one(p, rho, phi, s, pass, pass);
-      if (st != FSP_OK) {
-        e = hipErrorLaunchFailure;
-        break;
+      float total = 0;
+      for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // r == 0 warms up
+        fsp_status st = pass > 0 ? solve_one(p, rho, phi, s, 0, pass - 1) : FSP_OK;
+        if (st == FSP_OK) e = hipEventRecord(e0, s);
+        if (st == FSP_OK && e == hipSuccess) st = solve_one(p, rho, phi, s, pass, pass);
+        if (st == FSP_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+        if (st == FSP_OK && e == hipSuccess && pass < 4) st = solve_one(p, rho, phi, s, pass + 1, 4);
+        if (st != FSP_OK) {
+          e = hipErrorLaunchFailure;
+          break;
+        }
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (r > 0) total += ms;
       }
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      ms /= reps;
+      const float ms = total / reps;
       if (times_ms) times_ms[pass * fsp::NUM_VARIANTS + v] = ms;
       if (e == hipSuccess && ms < best_ms) {
         best_ms = ms;
         best[pass] = v;
       }
     }
+  }
+  // the fused passes 1-3, against the sum of the best separate ones
+  if (e == hipSuccess && fused_supported(p)) {
+    auto time_range = [&](const int* sched, float* out) -> hipError_t {
+      for (int i = 0; i < 5; ++i) p->var[i] = sched[i];
+      hipError_t r = hipSuccess;
+      float total = 0;
+      for (int k = 0; k <= reps && r == hipSuccess; ++k) {
+        if (solve_one(p, rho, phi, s, 0, 0) != FSP_OK) return hipErrorLaunchFailure;
+        r = hipEventRecord(e0, s);
+        if (r == hipSuccess && solve_one(p, rho, phi, s, 1, 3) != FSP_OK) return hipErrorLaunchFailure;
+        if (r == hipSuccess) r = hipEventRecord(e1, s);
+        if (r == hipSuccess && solve_one(p, rho, phi, s, 4, 4) != FSP_OK) return hipErrorLaunchFailure;
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        float ms = 0;
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+        if (k > 0) total += ms;
+      }
+      *out = total / reps;
+      return r;
+    };
+    int fused[5] = {best[0], fsp::FUSED, fsp::FUSED, fsp::FUSED, best[4]};
+    float t_sep = 0, t_fused = 0;
+    e = time_range(best, &t_sep);
+    if (e == hipSuccess) e = time_range(fused, &t_fused);
+    if (times_ms) times_ms[5 * fsp::NUM_VARIANTS] = t_fused, times_ms[5 * fsp::NUM_VARIANTS + 1] = t_sep;
+    if (e == hipSuccess && t_fused < t_sep)
+      for (int i = 1; i <= 3; ++i) best[i] = fsp::FUSED;
+  } else if (times_ms) {
+    times_ms[5 * fsp::NUM_VARIANTS] = times_ms[5 * fsp::NUM_VARIANTS + 1] = 0.0f;
   }
   for (int i = 0; i < 5; ++i) p->var[i] = best[i];
   if (e0) (void)hipEventDestroy(e0);

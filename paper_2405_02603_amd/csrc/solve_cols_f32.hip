@@ -3,4 +3,5 @@
 
 namespace fsp {
 template hipError_t launch_col<float>(int, int, int, const ColArgs&, int, hipStream_t);
+template hipError_t launch_slab<float>(int, const SlabArgs&, int, hipStream_t);
 }  // namespace fsp

@@ -63,6 +63,26 @@ struct RowArgs {
 template <typename T>
 __device__ __forceinline__ cx<T> czero() { return {T(0), T(0)}; }
 
+// Store of a pass result.  Results that the next pass does not re-read soon
+// are streamed past the caches (non-temporal); the float32 axis-1 passes keep
+// normal stores, because their output is re-read by the next pass while it is
+// still in the memory-side cache.
+enum PassKind { PASS_ROW_FWD, PASS_COL_FWD, PASS_CONV, PASS_COL_INV, PASS_ROW_INV };
+
+template <typename T, int KIND>
+__device__ __forceinline__ void put(cx<T>* p, cx<T> v) {
+  constexpr bool streamed = sizeof(T) == 8 || (KIND != PASS_COL_FWD && KIND != PASS_COL_INV);
+  if constexpr (streamed) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<v2*>(p));
+  } else {
+    *p = v;
+  }
+}
+
 // LDS slot of element e of a row in the row passes: one pad slot after every
 // 16 elements, so Stockham writes at strides of 16 or 32 elements fall on
 // distinct banks.
@@ -116,7 +136,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
       if (cok && ((F::NB % NQ == 0) || b < F::NB)) {
 #pragma unroll
         for (int m = 0; m < F::R; ++m)
-          if (!INV || m < F::R / 2) base[(b + m * F::NB) * rs] = v[j][m];
+          if (!INV || m < F::R / 2) put<T, INV ? PASS_COL_INV : PASS_COL_FWD>(&base[(b + m * F::NB) * rs], v[j][m]);
       }
     }
   } else {
@@ -133,7 +153,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
       if (cok && ((Ls::NB % NQ == 0) || b < Ls::NB)) {
 #pragma unroll
         for (int m = 0; m < Ls::R; ++m)
-          if (!INV || m < Ls::R / 2) base[(b + m * Ls::NB) * rs] = w[j][m];
+          if (!INV || m < Ls::R / 2) put<T, INV ? PASS_COL_INV : PASS_COL_FWD>(&base[(b + m * Ls::NB) * rs], w[j][m]);
       }
     }
   }
@@ -208,7 +228,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
           for (int m = 0; m < F::R; ++m) v[j][m] = cscale(v[j][m], gv[j][m]);
           Dft<F::R, true, T>::run(v[j]);
 #pragma unroll
-          for (int m = 0; m < F::R / 2; ++m) base[(b + m * F::NB) * rs] = v[j][m];
+          for (int m = 0; m < F::R / 2; ++m) put<T, PASS_CONV>(&base[(b + m * F::NB) * rs], v[j][m]);
         }
       }
     } else {
@@ -235,7 +255,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
         const int b = q + NQ * j;
         if (cok && ((Li::NB % NQ == 0) || b < Li::NB)) {
 #pragma unroll
-          for (int m = 0; m < Li::R / 2; ++m) base[(b + m * Li::NB) * rs] = u[j][m];
+          for (int m = 0; m < Li::R / 2; ++m) put<T, PASS_CONV>(&base[(b + m * Li::NB) * rs], u[j][m]);
         }
       }
     }
@@ -247,6 +267,332 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   if (two) {
     lds_barrier();
     run_set(base_b, raw_b);
+  }
+}
+
+// ----------------------------------------------------------------- P3, pipelined
+// Same computation as k_col_conv, but each block walks a sequence of pencil
+// sets (items blockIdx.x, blockIdx.x + gridDim.x, ...; each item is the k1
+// pair p, 2 n1 - p of one column tile) and loads the next set while it
+// transforms the current one, so memory traffic and arithmetic overlap inside
+// one block.  The Green's rows of a set are loaded at the start of its
+// transform (the second set of a pair finds them in cache).
+template <typename T, int L, int PID, int TC, int NQ>
+__global__ __launch_bounds__(TC* NQ) void k_col_conv_pipe(ColArgs a) {
+  constexpr int K = plan_len(L, PID);
+  static_assert(K > 1, "pipelined pass needs an LDS exchange");
+  __shared__ cx<T> lds[L * TC];
+  const int tid = threadIdx.x;
+  const int c = tid % TC, q = tid / TC;
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
+  auto idx = [c](int row) { return row * TC + c; };
+  using F = FirstStage<L, PID, false, NQ>;
+  using Lf = LastStage<L, PID, false, NQ>;
+  using Li = LastStage<L, PID, true, NQ>;
+  static_assert(F::R % 2 == 0 && Li::R % 2 == 0, "plans start with an even radix");
+  const int nitems = a.nouter * a.ntiles;
+  cx<T>* data = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]);
+  const T* ghat = reinterpret_cast<const T*>(a.ghat[blockIdx.y]);
+
+  // pencil set (item w, which) of this thread: its column base and Green's rows
+  auto set_base = [&](int w, int which) -> cx<T>* {
+    const int tile = w % a.ntiles, p = w / a.ntiles;
+    const int k1 = which == 0 ? p : 2 * a.n1 - p;
+    return data + (long long)k1 * a.outer_stride + (a.col0 + tile * TC + c);
+  };
+  auto set_green = [&](int w) -> const T* {
+    const int tile = w % a.ntiles, p = w / a.ntiles;
+    const int col = a.col0 + tile * TC + c;
+    return ghat + (long long)p * a.g_k1_stride + (long long)(col / TC) * (L / 2 + 1) * TC + (col % TC);
+  };
+  auto set_ok = [&](int w) { return a.col0 + (w % a.ntiles) * TC + c < a.ncols; };
+  auto paired = [&](int w) {
+    const int p = w / a.ntiles;
+    return p != 0 && p != a.n1;
+  };
+  auto load_set = [&](const cx<T>* base, bool on, cx<T> (&raw)[F::J][F::R / 2]) {
+#pragma unroll
+    for (int j = 0; j < F::J; ++j) {
+      const int b = q + NQ * j;
+      const bool ok = on && ((F::NB % NQ == 0) || b < F::NB);
+#pragma unroll
+      for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? base[(b + r * F::NB) * rs] : czero<T>();
+    }
+  };
+  auto run_set = [&](cx<T>* base, const T* g, bool on, const cx<T> (&raw)[F::J][F::R / 2]) {
+    cx<T> v[F::J][F::R];
+#pragma unroll
+    for (int j = 0; j < F::J; ++j) {
+#pragma unroll
+      for (int r = 0; r < F::R; ++r) v[j][r] = r < F::R / 2 ? raw[j][r] : czero<T>();
+      Dft<F::R, false, T>::run(v[j]);
+    }
+    write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+    lds_barrier();
+    lds_stages<T, L, PID, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
+    cx<T> w[Lf::J][Lf::R];
+    lds_last_stage<T, L, PID, false, NQ, false>(lds, tw, q, idx, w);
+#pragma unroll
+    for (int j = 0; j < Lf::J; ++j) {
+      const int b = q + NQ * j;
+      const bool ok = on && ((Lf::NB % NQ == 0) || b < Lf::NB);
+#pragma unroll
+      for (int m = 0; m < Lf::R; ++m) {
+        const int k0 = b + m * Lf::NB;
+        const int kf = k0 <= L / 2 ? k0 : L - k0;
+        w[j][m] = cscale(w[j][m], ok ? g[kf * TC] : T(0));
+      }
+      Dft<Lf::R, true, T>::run(w[j]);
+    }
+    lds_barrier();
+    write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, w, q, idx);
+    lds_barrier();
+    lds_stages<T, L, PID, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
+    cx<T> u[Li::J][Li::R];
+    lds_last_stage<T, L, PID, true, NQ, true>(lds, tw, q, idx, u);
+#pragma unroll
+    for (int j = 0; j < Li::J; ++j) {
+      const int b = q + NQ * j;
+      if (on && ((Li::NB % NQ == 0) || b < Li::NB)) {
+#pragma unroll
+        for (int m = 0; m < Li::R / 2; ++m) put<T, PASS_CONV>(&base[(b + m * Li::NB) * rs], u[j][m]);
+      }
+    }
+  };
+
+  int w = blockIdx.x, which = 0;
+  if (w >= nitems) return;  // uniform per block
+  cx<T> raw[F::J][F::R / 2];
+  load_set(set_base(w, which), set_ok(w), raw);
+  while (true) {
+    int w2 = w, which2 = which + 1;
+    if (which2 == 2 || !paired(w)) {
+      w2 = w + gridDim.x;
+      which2 = 0;
+    }
+    const bool more = w2 < nitems;  // uniform per block
+    cx<T> raw2[F::J][F::R / 2];
+    if (more) load_set(set_base(w2, which2), set_ok(w2), raw2);
+    run_set(set_base(w, which), set_green(w), set_ok(w), raw);
+    if (!more) break;
+    lds_barrier();
+    w = w2;
+    which = which2;
+#pragma unroll
+    for (int j = 0; j < F::J; ++j)
+#pragma unroll
+      for (int r = 0; r < F::R / 2; ++r) raw[j][r] = raw2[j][r];
+  }
+}
+
+// ----------------------------------------------------------------- P2+P3+P4 fused (small grids)
+// One block holds the whole (i0, k1) slab of TC adjacent columns in LDS,
+// laid out [i0][k1][c] (c fastest), and performs the axis-1 forward transform,
+// the axis-0 forward transform, Green's multiply and inverse, and the axis-1
+// inverse transform there: S is read once and written once.  Every stage works
+// on all pencils of the slab at once: a thread takes the butterflies
+// u = tid + NT j (c fastest, then butterfly, then pencil), reads their inputs,
+// waits at a barrier, then writes their outputs in place.
+template <typename T, int L, int PID, bool REV, int S, int NP, int TC, int NT, bool INV, bool PAD, class PIDX>
+__device__ __forceinline__ void slab_stage(cx<T>* lds, const cx<T>* __restrict__ tw, int tid, PIDX pidx) {
+  constexpr int R = plan_radix(L, PID, REV, S);
+  constexpr int NS = plan_ns(L, PID, REV, S);
+  constexpr int NB = L / R;
+  constexpr int UNITS = NP * TC * NB;
+  constexpr int J = (UNITS + NT - 1) / NT;
+  const cx<T>* tws = tw + tw_base(L, PID, REV) + tw_stage_off(L, PID, REV, S);
+  cx<T> v[J][R];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int u = tid + NT * j;
+    if (UNITS % NT == 0 || u < UNITS) {
+      const int c = u % TC, b = (u / TC) % NB, pp = u / (TC * NB);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        v[j][r] = (PAD && r >= R / 2) ? czero<T>() : lds[pidx(pp, b + r * NB, c)];
+    }
+  }
+  lds_barrier();
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int u = tid + NT * j;
+    if (UNITS % NT == 0 || u < UNITS) {
+      const int c = u % TC, b = (u / TC) % NB, pp = u / (TC * NB);
+      apply_twiddles<T, R, NS, INV>(v[j], tws, b % NS);
+      Dft<R, INV, T>::run(v[j]);
+      const int base = (b / NS) * NS * R + (b % NS);
+#pragma unroll
+      for (int m = 0; m < R; ++m) lds[pidx(pp, base + m * NS, c)] = v[j][m];
+    }
+  }
+  lds_barrier();
+}
+
+// All stages of one transform of every pencil of the slab, in LDS.
+template <typename T, int L, int PID, bool REV, int S, int NP, int TC, int NT, bool INV, bool PAD, class PIDX>
+__device__ __forceinline__ void slab_fft(cx<T>* lds, const cx<T>* __restrict__ tw, int tid, PIDX pidx) {
+  if constexpr (S < plan_len(L, PID)) {
+    slab_stage<T, L, PID, REV, S, NP, TC, NT, INV, PAD && S == 0>(lds, tw, tid, pidx);
+    slab_fft<T, L, PID, REV, S + 1, NP, TC, NT, INV, PAD>(lds, tw, tid, pidx);
+  }
+}
+
+// N0 = L0 / 2, N1 = L1 / 2.  tw1: twiddles of length L1 (plan PID1), tw0: of
+// length L0 (plan PID0); ghat blocked in column tiles of GT.
+struct SlabArgs {
+  void* data[MAX_ITEMS];
+  const void* ghat[MAX_ITEMS];
+  const void* tw1;
+  const void* tw0;
+  long long plane;   // complex elements between S planes i0
+  int pitch;         // P
+  int ncols;         // n2 + 1
+  int ntiles;        // column tiles of TC
+  int gt;            // column tile of the Green's octant
+  long long g_k1_stride;
+};
+
+template <typename T, int L1, int PID1, int L0, int PID0, int TC, int NT>
+__global__ __launch_bounds__(NT) void k_slab_conv(SlabArgs a) {
+  constexpr int N0 = L0 / 2, N1 = L1 / 2;
+  __shared__ cx<T> lds[N0 * L1 * TC];
+  const int tid = threadIdx.x;
+  const int col0 = blockIdx.x * TC;
+  cx<T>* S = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]);
+  const T* ghat = reinterpret_cast<const T*>(a.ghat[blockIdx.y]);
+  const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(a.tw1);
+  const cx<T>* tw0 = reinterpret_cast<const cx<T>*>(a.tw0);
+  // load rows (i0, i1 < N1) of the tile
+  for (int e = tid; e < N0 * N1 * TC; e += NT) {
+    const int c = e % TC, i1 = (e / TC) % N1, i0 = e / (TC * N1);
+    const int col = col0 + c;
+    lds[(i0 * L1 + i1) * TC + c] = col < a.ncols ? S[i0 * a.plane + (long long)i1 * a.pitch + col] : czero<T>();
+  }
+  lds_barrier();
+  // axis-1 forward: pencils (i0, c) along k1; upper half of the inputs is padding
+  auto along1 = [](int i0, int k1, int c) { return (i0 * L1 + k1) * TC + c; };
+  slab_fft<T, L1, PID1, false, 0, N0, TC, NT, false, true>(lds, tw1, tid, along1);
+  // axis 0: pencils (k1, c) along i0 (length L0, rows >= N0 live only in registers)
+  {
+    using F = FirstStage<L0, PID0, false, 1>;
+    constexpr int K = plan_len(L0, PID0);
+    static_assert(K >= 1, "plan");
+    // The axis-0 pencils are longer than the slab holds (rows N0..L0-1 are the
+    // zero padding and the discarded half), so each is transformed in registers
+    // by one thread group: NQ0 threads per pencil, pencils in turn.
+    constexpr int NQ0 = (L0 / F::R) < (NT / TC) ? (L0 / F::R) : (NT / TC);
+    // pencils of one column handled together, limited so that slab + scratch fit in LDS
+    constexpr int SLAB_BYTES = N0 * L1 * TC * (int)sizeof(cx<T>);
+    constexpr int PEN_ONE = TC * L0 * (int)sizeof(cx<T>);
+    constexpr int G_THREADS = NT / (NQ0 * TC);
+    constexpr int G_LDS = (163840 - 1024 - SLAB_BYTES) / PEN_ONE - 1;
+    constexpr int GROUPS = G_THREADS < G_LDS ? G_THREADS : (G_LDS > 0 ? G_LDS : 1);
+    // one extra group of scratch: threads beyond GROUPS groups run the same
+    // stage code (every thread takes the barriers) on that dummy region
+    __shared__ cx<T> pen[K > 1 ? (GROUPS + 1) * TC * L0 : 1];
+    const int c = tid % TC, q = (tid / TC) % NQ0, gsel = tid / (TC * NQ0);
+    const int gpen = gsel < GROUPS ? gsel : GROUPS;
+    auto pidx = [&](int row) { return (gpen * L0 + row) * TC + c; };
+    for (int k1b = 0; k1b < L1; k1b += GROUPS) {
+      const int k1 = k1b + gsel;
+      const bool act = gsel < GROUPS && k1 < L1 && tid < GROUPS * TC * NQ0;
+      const int col = col0 + c;
+      // forward first stage from the slab
+      cx<T> v[F::J][F::R];
+#pragma unroll
+      for (int j = 0; j < F::J; ++j) {
+        const int b = q + NQ0 * j;
+        const bool ok = act && ((F::NB % NQ0 == 0) || b < F::NB);
+#pragma unroll
+        for (int r = 0; r < F::R; ++r)
+          v[j][r] = (ok && r < F::R / 2) ? lds[(b + r * F::NB) * L1 * TC + k1 * TC + c] : czero<T>();
+        Dft<F::R, false, T>::run(v[j]);
+      }
+      if constexpr (K == 1) {
+        const int k1f = k1 <= N1 ? k1 : L1 - k1;
+        const T* g = ghat + (long long)k1f * a.g_k1_stride + (long long)(col / a.gt) * (N0 + 1) * a.gt + (col % a.gt);
+#pragma unroll
+        for (int j = 0; j < F::J; ++j) {
+          const int b = q + NQ0 * j;
+          const bool ok = act && col < a.ncols && ((F::NB % NQ0 == 0) || b < F::NB);
+#pragma unroll
+          for (int m = 0; m < F::R; ++m) {
+            const int k0 = b + m * F::NB;
+            const int kf = k0 <= N0 ? k0 : L0 - k0;
+            v[j][m] = cscale(v[j][m], ok ? g[kf * a.gt] : T(0));
+          }
+          Dft<F::R, true, T>::run(v[j]);
+        }
+        lds_barrier();
+#pragma unroll
+        for (int j = 0; j < F::J; ++j) {
+          const int b = q + NQ0 * j;
+          if (act && ((F::NB % NQ0 == 0) || b < F::NB)) {
+#pragma unroll
+            for (int m = 0; m < F::R / 2; ++m) lds[(b + m * F::NB) * L1 * TC + k1 * TC + c] = v[j][m];
+          }
+        }
+        lds_barrier();
+      } else {
+        using Lf = LastStage<L0, PID0, false, NQ0>;
+        using Li = LastStage<L0, PID0, true, NQ0>;
+        using F2 = FirstStage<L0, PID0, false, NQ0>;
+        cx<T> v2[F2::J][F2::R];
+#pragma unroll
+        for (int j = 0; j < F2::J; ++j) {
+          const int b = q + NQ0 * j;
+          const bool ok = act && ((F2::NB % NQ0 == 0) || b < F2::NB);
+#pragma unroll
+          for (int r = 0; r < F2::R; ++r)
+            v2[j][r] = (ok && r < F2::R / 2) ? lds[(b + r * F2::NB) * L1 * TC + k1 * TC + c] : czero<T>();
+          Dft<F2::R, false, T>::run(v2[j]);
+        }
+        write_first_outputs<T, F2::R, F2::J, F2::NB, NQ0>(pen, v2, q, pidx);
+        lds_barrier();
+        lds_stages<T, L0, PID0, false, 1, K - 1, NQ0, false>(pen, tw0, q, pidx);
+        cx<T> w[Lf::J][Lf::R];
+        lds_last_stage<T, L0, PID0, false, NQ0, false>(pen, tw0, q, pidx, w);
+        const int k1f = k1 <= N1 ? k1 : L1 - k1;
+        const T* g = ghat + (long long)k1f * a.g_k1_stride + (long long)(col / a.gt) * (N0 + 1) * a.gt + (col % a.gt);
+#pragma unroll
+        for (int j = 0; j < Lf::J; ++j) {
+          const int b = q + NQ0 * j;
+          const bool ok = act && col < a.ncols && ((Lf::NB % NQ0 == 0) || b < Lf::NB);
+#pragma unroll
+          for (int m = 0; m < Lf::R; ++m) {
+            const int k0 = b + m * Lf::NB;
+            const int kf = k0 <= N0 ? k0 : L0 - k0;
+            w[j][m] = cscale(w[j][m], ok ? g[kf * a.gt] : T(0));
+          }
+          Dft<Lf::R, true, T>::run(w[j]);
+        }
+        lds_barrier();
+        write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ0>(pen, w, q, pidx);
+        lds_barrier();
+        lds_stages<T, L0, PID0, true, 1, K - 1, NQ0, true>(pen, tw0, q, pidx);
+        cx<T> u[Li::J][Li::R];
+        lds_last_stage<T, L0, PID0, true, NQ0, true>(pen, tw0, q, pidx, u);
+        // back into the slab, rows < N0 (all of this group's reads of the slab are done)
+#pragma unroll
+        for (int j = 0; j < Li::J; ++j) {
+          const int b = q + NQ0 * j;
+          if (act && ((Li::NB % NQ0 == 0) || b < Li::NB)) {
+#pragma unroll
+            for (int m = 0; m < Li::R / 2; ++m) lds[(b + m * Li::NB) * L1 * TC + k1 * TC + c] = u[j][m];
+          }
+        }
+        lds_barrier();
+      }
+    }
+  }
+  // axis-1 inverse: pencils (i0, c) along k1, in LDS
+  slab_fft<T, L1, PID1, true, 0, N0, TC, NT, true, false>(lds, tw1, tid, along1);
+  // store rows (i0, i1 < N1)
+  for (int e = tid; e < N0 * N1 * TC; e += NT) {
+    const int c = e % TC, i1 = (e / TC) % N1, i0 = e / (TC * N1);
+    const int col = col0 + c;
+    if (col < a.ncols) put<T, PASS_COL_INV>(&S[i0 * a.plane + (long long)i1 * a.pitch + col], lds[(i0 * L1 + i1) * TC + c]);
   }
 }
 
@@ -312,7 +658,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
       const cx<T> E = {T(0.5) * (A.x + B.x), T(0.5) * (A.y + B.y)};
       const cx<T> D = {T(0.5) * (A.x - B.x), T(0.5) * (A.y - B.y)};
       const cx<T> U = cmul(pp[k], D);
-      out[k] = {E.x + U.y, E.y - U.x};
+      put<T, PASS_ROW_FWD>(&out[k], cx<T>{E.x + U.y, E.y - U.x});
     }
   }
 }
@@ -372,7 +718,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
         const int b = q + NQ * j;
         if ((F::NB % NQ == 0) || b < F::NB) {
 #pragma unroll
-          for (int m = 0; m < F::R / 2; ++m) out[b + m * F::NB] = v[j][m];
+          for (int m = 0; m < F::R / 2; ++m) put<T, PASS_ROW_INV>(&out[b + m * F::NB], v[j][m]);
         }
       }
     }
@@ -391,7 +737,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
         const int b = q + NQ * j;
         if ((Li::NB % NQ == 0) || b < Li::NB) {
 #pragma unroll
-          for (int m = 0; m < Li::R / 2; ++m) out[b + m * Li::NB] = u[j][m];
+          for (int m = 0; m < Li::R / 2; ++m) put<T, PASS_ROW_INV>(&out[b + m * Li::NB], u[j][m]);
         }
       }
     }

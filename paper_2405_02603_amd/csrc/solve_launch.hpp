@@ -34,6 +34,9 @@ __host__ __device__ constexpr int col_tc(int L) {
 template <typename T>
 __host__ __device__ constexpr TileCfg col_cfg(int L, int v) {
   const int tc = col_tc<T>(L);
+  // wider tiles (longer row segments, more LDS) for variant 2 of the long pencils;
+  // the axis-0 pass never uses this shape (its variant 2 is the pipelined kernel)
+  const int tw = 2 * tc;
   switch (L) {
     case 16: return v == 0 ? TileCfg{0, tc, 1} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{1, tc, 2};
     case 24: return v == 0 ? TileCfg{0, tc, 1} : v == 1 ? TileCfg{1, tc, 2} : TileCfg{0, tc, 3};
@@ -43,11 +46,11 @@ __host__ __device__ constexpr TileCfg col_cfg(int L, int v) {
     case 96: return v == 0 ? TileCfg{0, tc, 4} : v == 1 ? TileCfg{1, tc, 2} : TileCfg{0, tc, 8};
     case 128: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 8} : TileCfg{0, tc, 16};
     case 192: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{0, tc, 16};
-    case 256: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tc, 8};
-    case 384: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 8} : TileCfg{0, tc, 16};
-    case 512: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{1, tc, 16};
-    case 768: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 16} : TileCfg{0, tc, 32};
-    case 1024: return v == 0 ? TileCfg{0, tc, 32} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tc, 16};
+    case 256: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tw, 16};
+    case 384: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 8} : TileCfg{0, tw, 8};
+    case 512: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tw, 16};
+    case 768: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 16} : TileCfg{0, tw, 16};
+    case 1024: return v == 0 ? TileCfg{0, tc, 32} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tw, 32};
     default: return {0, 0, 0};
   }
 }
@@ -72,6 +75,21 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
     case 512: return v == 0 ? TileCfg{0, d ? 4 : 8, 16} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{0, d ? 8 : 16, 16};
     default: return {0, 0, 0};
   }
+}
+
+// Axis-0 pass variants: as col_cfg, except that variant 2 of the longer pencils
+// is the pipelined persistent kernel (grid of at most CONV_PIPE_BLOCKS blocks)
+// with the tile shape of variant 1.
+constexpr int CONV_PIPE_BLOCKS = 1024;
+
+template <typename T>
+__host__ __device__ constexpr bool conv_pipelined(int L, int v) {
+  return v == 2 && L >= 128 && plan_len(L, col_cfg<T>(L, 0).pid) > 1;
+}
+
+template <typename T>
+__host__ __device__ constexpr TileCfg conv_cfg(int L, int v) {
+  return conv_pipelined<T>(L, v) ? col_cfg<T>(L, 1) : col_cfg<T>(L, v);
 }
 
 #define FSP_ROW_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
@@ -127,11 +145,18 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
 #define FSP_CASE_V(LV, VV)                                                                          \
   if (L == LV && v == VV) {                                                                         \
     constexpr TileCfg c = col_cfg<T>(LV, VV);                                                       \
+    constexpr TileCfg cc = conv_cfg<T>(LV, VV);                                                     \
     const dim3 grid((unsigned)(a.nouter * a.ntiles), (unsigned)items);                              \
     const dim3 block(c.tiles * c.nq);                                                               \
-    if (kind == 2)                                                                                  \
-      hipLaunchKernelGGL((k_col_conv<T, LV, c.pid, c.tiles, c.nq>), grid, block, 0, s, a);          \
-    else if (kind == 1)                                                                             \
+    if (kind == 2) {                                                                                \
+      if constexpr (conv_pipelined<T>(LV, VV)) {                                                    \
+        const int nb = a.nouter * a.ntiles < CONV_PIPE_BLOCKS ? a.nouter * a.ntiles : CONV_PIPE_BLOCKS; \
+        hipLaunchKernelGGL((k_col_conv_pipe<T, LV, cc.pid, cc.tiles, cc.nq>), dim3(nb, items),      \
+                           dim3(cc.tiles * cc.nq), 0, s, a);                                        \
+      } else {                                                                                      \
+        hipLaunchKernelGGL((k_col_conv<T, LV, c.pid, c.tiles, c.nq>), grid, block, 0, s, a);        \
+      }                                                                                             \
+    } else if (kind == 1)                                                                           \
       hipLaunchKernelGGL((k_col_fft<T, LV, c.pid, c.tiles, c.nq, true>), grid, block, 0, s, a);     \
     else                                                                                            \
       hipLaunchKernelGGL((k_col_fft<T, LV, c.pid, c.tiles, c.nq, false>), grid, block, 0, s, a);    \
@@ -145,6 +170,46 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
   return hipGetLastError();
 }
 
+// Fused axis-1 / axis-0 / axis-1 schedule for small cubic grids (n0 == n1):
+// one block per TC columns holds the (i0, k1) slab in LDS.  tiles == 0 means
+// unsupported.  LDS = (n N TC + groups TC 2n) sizeof(cx<T>) <= 160 KB.
+constexpr int FUSED = 3;  // schedule value of passes 1..3 selecting the fused kernel
+
+template <typename T>
+__host__ __device__ constexpr TileCfg slab_cfg(int L) {
+  constexpr bool d = sizeof(T) == 8;
+  switch (L) {
+    case 16: return {0, d ? 16 : 32, 512};
+    case 24: return {0, d ? 8 : 16, 512};
+    case 32: return {0, d ? 8 : 16, 512};
+    case 48: return {0, d ? 4 : 8, 512};
+    case 64: return {0, d ? 2 : 4, 512};
+    case 96: return {0, d ? 1 : 2, 512};
+    case 128: return d ? TileCfg{0, 0, 0} : TileCfg{0, 2, 256};
+    default: return {0, 0, 0};
+  }
+}
+
+#define FSP_SLAB_LENGTHS(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
+
+template <typename T>
+hipError_t launch_slab(int L, const SlabArgs& a, int items, hipStream_t s) {
+  bool found = false;
+#define FSP_CASE(LV)                                                                                \
+  if (L == LV) {                                                                                    \
+    constexpr TileCfg c = slab_cfg<T>(LV);                                                          \
+    if constexpr (c.tiles > 0) {                                                                    \
+      hipLaunchKernelGGL((k_slab_conv<T, LV, 0, LV, 0, c.tiles, c.nq>), dim3(a.ntiles, items),      \
+                         dim3(c.nq), 0, s, a);                                                      \
+      found = true;                                                                                 \
+    }                                                                                               \
+  }
+  FSP_SLAB_LENGTHS(FSP_CASE)
+#undef FSP_CASE
+  if (!found) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 #ifdef FSP_SPLIT_LAUNCHERS
 // The launchers are instantiated in their own translation units (compiled in
 // parallel); the solve driver only references them.
@@ -154,6 +219,8 @@ extern template hipError_t launch_col<float>(int, int, int, const ColArgs&, int,
 extern template hipError_t launch_p1<double>(int, int, const RowArgs&, int, hipStream_t);
 extern template hipError_t launch_p5<double>(int, int, const RowArgs&, int, hipStream_t);
 extern template hipError_t launch_col<double>(int, int, int, const ColArgs&, int, hipStream_t);
+extern template hipError_t launch_slab<float>(int, const SlabArgs&, int, hipStream_t);
+extern template hipError_t launch_slab<double>(int, const SlabArgs&, int, hipStream_t);
 #endif
 
 // Geometry of up to MAX_ITEMS solves of one shape, filled by the plans.
@@ -208,7 +275,8 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
     const long long t0 = col_tiles<T>(2 * g.n0);
     cc.g_k1_stride = (g.n2 + 1 + t0 - 1) / t0 * (g.n0 + 1) * t0;
   }
-  const int tc1 = col_tiles<T>(2 * g.n1), tc0 = col_tiles<T>(2 * g.n0);
+  const int tc2 = col_cfg<T>(2 * g.n1, g.var[1]).tiles, tc4 = col_cfg<T>(2 * g.n1, g.var[3]).tiles;
+  const int tc0 = col_tiles<T>(2 * g.n0);
   const int ncols = g.n2 + 1;
   auto set_cols = [&](ColArgs& c, int tcw, int c0, int c1) {
     c.col0 = c0;
@@ -225,12 +293,12 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
         ra.tw = g.tw_row[0];
         return launch_p1<T>(g.n2, g.var[0], ra, g.items, s);
       case 1:
-        set_cols(ca, tc1, c0, c1);
+        set_cols(ca, tc2, c0, c1);
         ca.tw = g.tw_c1[1];
         return launch_col<T>(2 * g.n1, g.var[1], 0, ca, g.items, s);
       case 2: set_cols(cc, tc0, c0, c1); return launch_col<T>(2 * g.n0, g.var[2], 2, cc, g.items, s);
       case 3:
-        set_cols(ca, tc1, c0, c1);
+        set_cols(ca, tc4, c0, c1);
         ca.tw = g.tw_c1[3];
         return launch_col<T>(2 * g.n1, g.var[3], 1, ca, g.items, s);
       case 4:
@@ -244,11 +312,34 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
     }
   };
   hipError_t e = hipSuccess;
+  if (g.var[1] == FUSED) {
+    // passes 1-3 as one fused kernel over column tiles
+    if (first > 1 || last < 3) return hipErrorInvalidValue;
+    if (first == 0) e = run(0, 0, ncols);
+    if (e != hipSuccess) return e;
+    SlabArgs sa{};
+    for (int i = 0; i < g.items; ++i) {
+      sa.data[i] = g.work[i];
+      sa.ghat[i] = g.ghat[i];
+    }
+    sa.tw1 = g.tw_c1[1];
+    sa.tw0 = g.tw_c0;
+    sa.plane = g.plane;
+    sa.pitch = g.pitch;
+    sa.ncols = ncols;
+    const int tcs = slab_cfg<T>(2 * g.n1).tiles;
+    sa.ntiles = (ncols + tcs - 1) / tcs;
+    sa.gt = tc0;
+    sa.g_k1_stride = cc.g_k1_stride;
+    e = launch_slab<T>(2 * g.n1, sa, g.items, s);
+    if (e == hipSuccess && last == 4) e = run(4, 0, ncols);
+    return e;
+  }
   if (g.chunks > 1 && first <= 1 && last >= 3) {
     // passes 1-3 column chunk by column chunk: a chunk's spectrum stays in the
     // memory-side cache between the three passes
     if (first == 0) e = run(0, 0, ncols);
-    const int step = tc1 > tc0 ? tc1 : tc0;
+    const int step = tc2 > tc0 ? (tc2 > tc4 ? tc2 : tc4) : (tc0 > tc4 ? tc0 : tc4);
     const int width = ((ncols + g.chunks - 1) / g.chunks + step - 1) / step * step;
     for (int c0 = 0; c0 < ncols && e == hipSuccess; c0 += width) {
       const int c1 = c0 + width < ncols ? c0 + width : ncols;

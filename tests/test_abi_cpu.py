@@ -136,3 +136,25 @@ def test_buffer_sizes_and_model_bytes(lib, prec, rb, n):
 def test_status_strings(lib):
     for code in range(7):
         assert lib.fsp_status_str(code).decode().startswith("FSP_")
+
+
+def test_schedule_validation(lib):
+    st, h = _create(lib, _desc(n=32))
+    assert st == _lib.FSP_OK
+    arr = (ctypes.c_int * 5)()
+    assert lib.fsp_plan_get_schedule(h, arr) == _lib.FSP_OK
+    assert list(arr) == [0, 0, 0, 0, 0]
+    ok = (ctypes.c_int * 5)(2, 1, 0, 2, 1)
+    assert lib.fsp_plan_set_schedule(h, ok) == _lib.FSP_OK
+    fused = (ctypes.c_int * 5)(0, 3, 3, 3, 0)
+    assert lib.fsp_plan_set_schedule(h, fused) == _lib.FSP_OK
+    for bad in ((0, 3, 0, 3, 0), (3, 0, 0, 0, 0), (0, 0, 0, 0, 4), (-1, 0, 0, 0, 0)):
+        assert lib.fsp_plan_set_schedule(h, (ctypes.c_int * 5)(*bad)) == _lib.FSP_ERR_INVALID_ARG
+    lib.fsp_plan_destroy(h)
+    # the fused schedule needs n0 == n1 and a slab that fits in LDS
+    st, h = _create(lib, _desc(n=(32, 64, 32)))
+    assert lib.fsp_plan_set_schedule(h, fused) == _lib.FSP_ERR_INVALID_ARG
+    lib.fsp_plan_destroy(h)
+    st, h = _create(lib, _desc(n=256))
+    assert lib.fsp_plan_set_schedule(h, fused) == _lib.FSP_ERR_INVALID_ARG
+    lib.fsp_plan_destroy(h)

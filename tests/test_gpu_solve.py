@@ -145,7 +145,8 @@ def test_autotune_256(torch_cuda, prec):
     r = to_dev(rho, dt)
     times = plan.autotune(r, reps=2)
     torch.cuda.synchronize()
-    assert all(t > 0 for ts in times.values() for t in ts)
+    assert all(t > 0 for p in range(5) for t in times[p])
+    assert times["fused_1_3"] == 0.0          # 256^3 is too large for the fused slab schedule
     sched = plan.schedule
     for p in range(5):
         assert times[p][sched[p]] == min(times[p])
@@ -154,8 +155,46 @@ def test_autotune_256(torch_cuda, prec):
     ref = reference(rho, "vico_dct", lo, hi, use_direct=False)
     assert rel_l2(to_host(phi), ref) <= (F64_TOL if prec == "f64" else F32_TOL)
     for v in range(3):
-        plan.schedule = [v] * 5
+        plan.schedule = [v] * 5  # every variant at the benchmark size
         phi = plan.solve(r)
         torch.cuda.synchronize()
         assert rel_l2(to_host(phi), ref) <= (F64_TOL if prec == "f64" else F32_TOL), f"variant {v}"
-    print("autotune", prec, sched, {p: [round(t, 4) for t in ts] for p, ts in times.items()})
+    print("autotune", prec, sched, {p: [round(t, 4) for t in times[p]] for p in range(5)})
+
+
+@pytest.mark.parametrize("prec,tol,sizes", [("f32", F32_TOL, (8, 12, 16, 24, 32, 48, 64)),
+                                            ("f64", F64_TOL, (8, 12, 16, 24, 32, 48))])
+def test_fused_small_grid_schedule(torch_cuda, prec, tol, sizes):
+    """The fused passes 1-3 (slab in LDS) give the oracle's result, for both kernels."""
+    from paper_2405_02603_amd import _lib
+    torch = torch_cuda
+    dt = torch.float64 if prec == "f64" else torch.float32
+    for n in sizes:
+        for kind in ("hockney", "vico_dct"):
+            lo, hi = (-1.0, -1.0, -0.5), (1.0, 1.0, 1.5)
+            rho = W.random_field((n, n, n), 17 + n)
+            ref = reference(rho, kind, lo, hi, use_direct=n <= 16)
+            plan = _plan(n, lo, hi, kind, prec)
+            plan.schedule = [0, _lib.FUSED, _lib.FUSED, _lib.FUSED, 0]
+            phi = plan.solve(to_dev(rho, dt))
+            torch.cuda.synchronize()
+            assert rel_l2(to_host(phi), ref) <= tol, (n, kind)
+
+
+def test_fused_schedule_in_batch_and_anisotropic_n2(torch_cuda):
+    """Fused plans in a batched launch; n2 may differ from n0 == n1."""
+    from paper_2405_02603_amd import _lib, solve_batched
+    torch = torch_cuda
+    plans, rhos, refs = [], [], []
+    for i, n in enumerate([(32, 32, 48), (32, 32, 48), (16, 16, 8)]):
+        lo, hi = (-1.0,) * 3, (1.0,) * 3
+        rho = W.random_field(n, 30 + i)
+        p = _plan(n, lo, hi, "vico_dct", "f32")
+        p.schedule = [0, _lib.FUSED, _lib.FUSED, _lib.FUSED, 0]
+        plans.append(p)
+        rhos.append(to_dev(rho, torch.float32))
+        refs.append(reference(rho, "vico_dct", lo, hi, use_direct=False))
+    outs = solve_batched(plans, rhos)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, refs):
+        assert rel_l2(to_host(o), r) <= F32_TOL
