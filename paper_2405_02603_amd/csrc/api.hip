@@ -92,6 +92,23 @@ void append_twiddles(std::vector<char>& buf, int L, int pid) {
   }
 }
 
+// Complete table of one plan (fsp::twf_stage_off order): w^(r k) for each stage.
+template <typename T>
+void append_full_twiddles(std::vector<char>& buf, int L, int pid) {
+  for (int rev = 0; rev < 2; ++rev) {
+    for (int s = 1; s < fsp::plan_len(L, pid); ++s) {
+      const int R = fsp::plan_radix(L, pid, rev != 0, s);
+      const int NS = fsp::plan_ns(L, pid, rev != 0, s);
+      for (int k = 0; k < NS; ++k)
+        for (int r = 1; r < R; ++r) {
+          long double c, sn;
+          cis_neg((long long)k * r, (long long)NS * R, &c, &sn);
+          push_c<T>(buf, c, sn);
+        }
+    }
+  }
+}
+
 // DCT-I rows m < nout of a length period+1 transform: C[m][l] = w_l cos(pi l m / period),
 // w_0 = w_period = 1, else 2.
 void dct1_matrix(std::vector<double>& C, int nout, int period) {
@@ -185,6 +202,7 @@ void build_twiddles(fsp_plan_s* p) {
   for (int pid = 0; pid < fsp::NUM_PLANS; ++pid) {
     p->tw_c0_off[pid] = b.size();
     append_twiddles<T>(b, 2 * p->n[0], pid);
+    append_full_twiddles<T>(b, 2 * p->n[0], pid);  // read by the axis-0 kernel's LDS-table variant
     b.resize(align_up(b.size(), 256), 0);
   }
   p->oct_off = b.size();
@@ -536,7 +554,9 @@ static fsp::SolveGeom group_geom(const fsp_plan_s* p) {
   const bool fused = p->var[1] == fsp::FUSED;
   const int pc2 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], p->var[1]).pid;
   const int pc4 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], p->var[3]).pid;
-  const int pc3 = fused ? 0 : fsp::conv_cfg<float>(2 * p->n[0], p->var[2]).pid;
+  const int pc3 = fused                     ? 0
+                  : p->d.prec == FSP_F64 ? fsp::conv_cfg<double>(2 * p->n[0], p->var[2]).pid
+                                              : fsp::conv_cfg<float>(2 * p->n[0], p->var[2]).pid;
   for (int i = 0; i < 5; ++i) g.tw_row[i] = g.tw_c1[i] = nullptr;
   g.tw_row[0] = gb + p->tw_row_off[pr1];
   g.tw_row[4] = gb + p->tw_row_off[pr5];

@@ -117,6 +117,22 @@ __host__ __device__ constexpr int tw_base(int L, int pid, bool rev) {
   return rev ? tw_order_size(L, pid, false) : 0;
 }
 
+// Complete twiddle table of one plan, for kernels that keep it in LDS: stage
+// s >= 1 of an order holds w^(r k) for k in [0, NS) and r in [1, R) at
+// k (R - 1) + r - 1 (so butterflies read from different LDS banks); forward
+// order, then reversed order.  It follows the six-power table.
+__host__ __device__ constexpr int twf_stage_size(int L, int pid, bool rev, int s) {
+  return plan_ns(L, pid, rev, s) * (plan_radix(L, pid, rev, s) - 1);
+}
+__host__ __device__ constexpr int twf_stage_off(int L, int pid, bool rev, int s) {
+  int off = 0;
+  if (rev)
+    for (int i = 1; i < plan_len(L, pid); ++i) off += twf_stage_size(L, pid, false, i);
+  for (int i = 1; i < s; ++i) off += twf_stage_size(L, pid, rev, i);
+  return off;
+}
+__host__ __device__ constexpr int twf_size(int L, int pid) { return twf_stage_off(L, pid, true, plan_len(L, pid)); }
+
 // ---------------------------------------------------------------- complex
 template <typename T>
 struct cx {
@@ -357,15 +373,36 @@ __device__ __forceinline__ void apply_twiddles(cx<T>* v, const cx<T>* __restrict
   }
 }
 
+// v[r] *= w^(r k) or its conjugate from the complete table of the stage.
+template <typename T, int R, int NS, bool INV>
+__device__ __forceinline__ void apply_twiddles_full(cx<T>* v, const cx<T>* tf, int k) {
+  if constexpr (NS > 1) {
+    const cx<T>* e = tf + k * (R - 1) - 1;
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], e[r]) : cmul(v[r], e[r]);
+  }
+}
+
+// Twiddles of stage S: from the six-power table tw (FULL == false) or from the
+// complete table at tw (FULL == true).
+template <typename T, int L, int PID, bool REV, int S, bool INV, bool FULL>
+__device__ __forceinline__ void stage_twiddles(cx<T>* v, const cx<T>* tw, int k) {
+  constexpr int R = plan_radix(L, PID, REV, S);
+  constexpr int NS = plan_ns(L, PID, REV, S);
+  if constexpr (FULL)
+    apply_twiddles_full<T, R, NS, INV>(v, tw + twf_stage_off(L, PID, REV, S), k);
+  else
+    apply_twiddles<T, R, NS, INV>(v, tw + tw_base(L, PID, REV) + tw_stage_off(L, PID, REV, S), k);
+}
+
 // One middle stage: inputs from LDS, outputs back to LDS (in place, two barriers).
 // idx(row) maps a pencil row to this thread's LDS slot.
-template <typename T, int L, int PID, bool REV, int S, int NQ, bool INV, class IDX>
+template <typename T, int L, int PID, bool REV, int S, int NQ, bool INV, bool FULL = false, class IDX>
 __device__ __forceinline__ void lds_stage(cx<T>* lds, const cx<T>* __restrict__ tw, int q, IDX idx) {
   constexpr int R = plan_radix(L, PID, REV, S);
   constexpr int NS = plan_ns(L, PID, REV, S);
   constexpr int NB = L / R;
   constexpr int J = (NB + NQ - 1) / NQ;
-  const cx<T>* tws = tw + tw_base(L, PID, REV) + tw_stage_off(L, PID, REV, S);
   cx<T> v[J][R];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -380,7 +417,7 @@ __device__ __forceinline__ void lds_stage(cx<T>* lds, const cx<T>* __restrict__ 
   for (int j = 0; j < J; ++j) {
     const int b = q + NQ * j;
     if ((NB % NQ == 0) || b < NB) {
-      apply_twiddles<T, R, NS, INV>(v[j], tws, b % NS);
+      stage_twiddles<T, L, PID, REV, S, INV, FULL>(v[j], tw, b % NS);
       Dft<R, INV, T>::run(v[j]);
       const int base = (b / NS) * NS * R + (b % NS);
 #pragma unroll
@@ -390,16 +427,16 @@ __device__ __forceinline__ void lds_stage(cx<T>* lds, const cx<T>* __restrict__ 
   lds_barrier();
 }
 
-template <typename T, int L, int PID, bool REV, int S, int SEND, int NQ, bool INV, class IDX>
+template <typename T, int L, int PID, bool REV, int S, int SEND, int NQ, bool INV, bool FULL = false, class IDX>
 __device__ __forceinline__ void lds_stages(cx<T>* lds, const cx<T>* __restrict__ tw, int q, IDX idx) {
   if constexpr (S < SEND) {
-    lds_stage<T, L, PID, REV, S, NQ, INV>(lds, tw, q, idx);
-    lds_stages<T, L, PID, REV, S + 1, SEND, NQ, INV>(lds, tw, q, idx);
+    lds_stage<T, L, PID, REV, S, NQ, INV, FULL>(lds, tw, q, idx);
+    lds_stages<T, L, PID, REV, S + 1, SEND, NQ, INV, FULL>(lds, tw, q, idx);
   }
 }
 
 // Last stage: inputs from LDS, outputs left in registers v[j][m] = row b + m L/R.
-template <typename T, int L, int PID, bool REV, int NQ, bool INV, int J, int R, class IDX>
+template <typename T, int L, int PID, bool REV, int NQ, bool INV, bool FULL = false, int J, int R, class IDX>
 __device__ __forceinline__ void lds_last_stage(const cx<T>* lds, const cx<T>* __restrict__ tw, int q,
                                                IDX idx, cx<T> (&v)[J][R]) {
   constexpr int S = plan_len(L, PID) - 1;
@@ -408,14 +445,13 @@ __device__ __forceinline__ void lds_last_stage(const cx<T>* lds, const cx<T>* __
   static_assert(R == plan_radix(L, PID, REV, S), "register array matches the last radix");
   static_assert(J == (NB + NQ - 1) / NQ, "register array matches the butterfly split");
   static_assert(NS == NB, "last stage spans the pencil");
-  const cx<T>* tws = tw + tw_base(L, PID, REV) + tw_stage_off(L, PID, REV, S);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int b = q + NQ * j;
     if ((NB % NQ == 0) || b < NB) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[j][r] = lds[idx(b + r * NB)];
-      apply_twiddles<T, R, NS, INV>(v[j], tws, b);
+      stage_twiddles<T, L, PID, REV, S, INV, FULL>(v[j], tw, b);
       Dft<R, INV, T>::run(v[j]);
     }
   }

@@ -160,16 +160,25 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
 }
 
 // ----------------------------------------------------------------- P3
-template <typename T, int L, int PID, int TC, int NQ>
+// TWF: the plan's complete twiddle table is read into LDS once per block, so
+// the butterflies load every power instead of multiplying it out of six.
+template <typename T, int L, int PID, int TC, int NQ, bool TWF = false>
 __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   constexpr int K = plan_len(L, PID);
+  static_assert(!TWF || K > 1, "single-stage plans have no twiddles");
   __shared__ cx<T> lds[K > 1 ? L * TC : 1];
+  __shared__ cx<T> twl[TWF ? twf_size(L, PID) : 1];
   const int tid = threadIdx.x;
   const int c = tid % TC, q = tid / TC;
   int col, p;  // p: k1 in [0, n1]; the thread also handles 2 n1 - p
   bool cok;
   place_column<TC>(a, c, col, p, cok);
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
+  if constexpr (TWF) {  // before the pencil loads, so waiting for it does not wait for them
+    const cx<T>* src = tw + tw_size(L, PID);
+    for (int e = tid; e < twf_size(L, PID); e += TC * NQ) twl[e] = src[e];
+    tw = twl;  // made visible by the barrier after the first stage's LDS writes
+  }
   const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
   auto idx = [c](int row) { return row * TC + c; };
   using F = FirstStage<L, PID, false, NQ>;   // forward, first stage
@@ -193,7 +202,6 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
     }
   }
 
-  // k1 = p and its partner 2 n1 - p share the Green's rows; p = 0 and p = n1 have no partner.
   // k1 = p and its partner 2 n1 - p share the Green's rows; p = 0 and p = n1
   // have no partner.  Both pencil sets are loaded before either is
   // transformed, so the second set's loads overlap the first set's work.
@@ -234,9 +242,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
     } else {
       write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
       lds_barrier();
-      lds_stages<T, L, PID, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
+      lds_stages<T, L, PID, false, 1, K - 1, NQ, false, TWF>(lds, tw, q, idx);
       cx<T> w[Lf::J][Lf::R];
-      lds_last_stage<T, L, PID, false, NQ, false>(lds, tw, q, idx, w);
+      lds_last_stage<T, L, PID, false, NQ, false, TWF>(lds, tw, q, idx, w);
       // multiply, then the first inverse stage (span 1) in registers
 #pragma unroll
       for (int j = 0; j < Lf::J; ++j) {
@@ -247,9 +255,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       lds_barrier();
       write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, w, q, idx);
       lds_barrier();
-      lds_stages<T, L, PID, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
+      lds_stages<T, L, PID, true, 1, K - 1, NQ, true, TWF>(lds, tw, q, idx);
       cx<T> u[Li::J][Li::R];
-      lds_last_stage<T, L, PID, true, NQ, true>(lds, tw, q, idx, u);
+      lds_last_stage<T, L, PID, true, NQ, true, TWF>(lds, tw, q, idx, u);
 #pragma unroll
       for (int j = 0; j < Li::J; ++j) {
         const int b = q + NQ * j;

@@ -77,19 +77,35 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
   }
 }
 
-// Axis-0 pass variants: as col_cfg, except that variant 2 of the longer pencils
-// is the pipelined persistent kernel (grid of at most CONV_PIPE_BLOCKS blocks)
-// with the tile shape of variant 1.
+// Axis-0 pass variants: variants 0 and 1 as col_cfg; variant 2 keeps the
+// complete twiddle table in LDS, with the shape of variant 0 (else 1) when the
+// table and the pencils fit in half of a compute unit's LDS, else it is the
+// pipelined persistent kernel (grid of at most CONV_PIPE_BLOCKS blocks) with
+// the shape of variant 1.
 constexpr int CONV_PIPE_BLOCKS = 1024;
+constexpr int CONV_TWF_LDS = 81920;
+
+template <typename T>
+__host__ __device__ constexpr bool conv_twf_fits(int L, int v) {
+  const TileCfg c = col_cfg<T>(L, v);
+  return plan_len(L, c.pid) > 1 && (L * c.tiles + twf_size(L, c.pid)) * 2 * (int)sizeof(T) <= CONV_TWF_LDS;
+}
+
+template <typename T>
+__host__ __device__ constexpr bool conv_twf(int L, int v) {
+  return v == 2 && (conv_twf_fits<T>(L, 0) || conv_twf_fits<T>(L, 1));
+}
 
 template <typename T>
 __host__ __device__ constexpr bool conv_pipelined(int L, int v) {
-  return v == 2 && L >= 128 && plan_len(L, col_cfg<T>(L, 0).pid) > 1;
+  return v == 2 && !conv_twf<T>(L, v) && L >= 128 && plan_len(L, col_cfg<T>(L, 1).pid) > 1;
 }
 
 template <typename T>
 __host__ __device__ constexpr TileCfg conv_cfg(int L, int v) {
-  return conv_pipelined<T>(L, v) ? col_cfg<T>(L, 1) : col_cfg<T>(L, v);
+  return conv_twf<T>(L, v) ? col_cfg<T>(L, conv_twf_fits<T>(L, 0) ? 0 : 1)
+         : conv_pipelined<T>(L, v) ? col_cfg<T>(L, 1)
+                                   : col_cfg<T>(L, v);
 }
 
 #define FSP_ROW_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
@@ -149,7 +165,10 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
     const dim3 grid((unsigned)(a.nouter * a.ntiles), (unsigned)items);                              \
     const dim3 block(c.tiles * c.nq);                                                               \
     if (kind == 2) {                                                                                \
-      if constexpr (conv_pipelined<T>(LV, VV)) {                                                    \
+      if constexpr (conv_twf<T>(LV, VV)) {                                                          \
+        hipLaunchKernelGGL((k_col_conv<T, LV, cc.pid, cc.tiles, cc.nq, true>), grid,                \
+                           dim3(cc.tiles * cc.nq), 0, s, a);                                        \
+      } else if constexpr (conv_pipelined<T>(LV, VV)) {                                             \
         const int nb = a.nouter * a.ntiles < CONV_PIPE_BLOCKS ? a.nouter * a.ntiles : CONV_PIPE_BLOCKS; \
         hipLaunchKernelGGL((k_col_conv_pipe<T, LV, cc.pid, cc.tiles, cc.nq>), dim3(nb, items),      \
                            dim3(cc.tiles * cc.nq), 0, s, a);                                        \
