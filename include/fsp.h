@@ -137,8 +137,8 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
  * the fused schedule for small grids with n0 == n1 (n <= 64 in float32, <= 48
  * in float64): one kernel holds a column tile's whole (axis 0, axis 1) slab in
  * LDS and runs passes 1-3 there; fsp_solve_passes then accepts only ranges
- * that contain all of 1-3.  Results are identical up to rounding order across
- * schedules.  A new plan starts with the schedule last tuned for its grid and
+ * that contain all of 1-3 or none of them (FSP_ERR_INVALID_ARG otherwise).
+ * Results are identical up to rounding order across schedules.  A new plan starts with the schedule last tuned for its grid and
  * precision in this process (else all zeros). */
 fsp_status fsp_plan_get_schedule(fsp_plan p, int* variants /* [5] */);
 fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants /* [5] */);
@@ -152,7 +152,8 @@ fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants /* [5] */);
  * `stream`.  times_ms (NULL or [5 * 3 + 2]) receives the average time of each
  * variant, times_ms[pass * 3 + variant], then the time of passes 1-3 fused and
  * of passes 1-3 with the best separate variants (0 when fusion is not
- * supported); the fused schedule is kept when it is faster. */
+ * supported); the fused schedule is kept when it is faster.  If a solve fails
+ * its status is returned and the plan keeps a valid (untuned) schedule. */
 fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* stream, float* times_ms);
 
 /* count independent solves (each with its own plan, and so its own

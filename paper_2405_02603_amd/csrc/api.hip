@@ -652,6 +652,8 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
   if (!p) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: NULL plan");
   if (first < 0 || last > 4 || first > last) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: need 0 <= first <= last <= 4");
   if ((first == 0 && !rho) || (last == 4 && !phi)) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: NULL rho/phi for its pass");
+  if (p->var[1] == fsp::FUSED && first <= 3 && last >= 1 && (first > 1 || last < 3))
+    return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: the fused schedule runs passes 1-3 together");
   if (!p->ready) return fail(FSP_ERR_NOT_READY, "fsp_solve_passes: plan has no bound buffers or no precomputed transform");
   DeviceGuard guard;
   hipError_t e = guard.enter(p->device);
@@ -716,9 +718,11 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
         if (st == FSP_OK && e == hipSuccess) st = solve_one(p, rho, phi, s, pass, pass);
         if (st == FSP_OK && e == hipSuccess) e = hipEventRecord(e1, s);
         if (st == FSP_OK && e == hipSuccess && pass < 4) st = solve_one(p, rho, phi, s, pass + 1, 4);
-        if (st != FSP_OK) {
-          e = hipErrorLaunchFailure;
-          break;
+        if (st != FSP_OK) {  // the solve's own error is the one reported
+          for (int i = 0; i < 5; ++i) p->var[i] = best[i];
+          if (e0) (void)hipEventDestroy(e0);
+          if (e1) (void)hipEventDestroy(e1);
+          return st;
         }
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0;
@@ -735,16 +739,17 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
   }
   // the fused passes 1-3, against the sum of the best separate ones
   if (e == hipSuccess && fused_supported(p)) {
+    fsp_status st_range = FSP_OK;
     auto time_range = [&](const int* sched, float* out) -> hipError_t {
       for (int i = 0; i < 5; ++i) p->var[i] = sched[i];
       hipError_t r = hipSuccess;
       float total = 0;
       for (int k = 0; k <= reps && r == hipSuccess; ++k) {
-        if (solve_one(p, rho, phi, s, 0, 0) != FSP_OK) return hipErrorLaunchFailure;
+        if ((st_range = solve_one(p, rho, phi, s, 0, 0)) != FSP_OK) return hipErrorInvalidValue;
         r = hipEventRecord(e0, s);
-        if (r == hipSuccess && solve_one(p, rho, phi, s, 1, 3) != FSP_OK) return hipErrorLaunchFailure;
+        if (r == hipSuccess && (st_range = solve_one(p, rho, phi, s, 1, 3)) != FSP_OK) return hipErrorInvalidValue;
         if (r == hipSuccess) r = hipEventRecord(e1, s);
-        if (r == hipSuccess && solve_one(p, rho, phi, s, 4, 4) != FSP_OK) return hipErrorLaunchFailure;
+        if (r == hipSuccess && (st_range = solve_one(p, rho, phi, s, 4, 4)) != FSP_OK) return hipErrorInvalidValue;
         if (r == hipSuccess) r = hipEventSynchronize(e1);
         float ms = 0;
         if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
@@ -758,6 +763,12 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
     e = time_range(best, &t_sep);
     if (e == hipSuccess) e = time_range(fused, &t_fused);
     if (times_ms) times_ms[5 * fsp::NUM_VARIANTS] = t_fused, times_ms[5 * fsp::NUM_VARIANTS + 1] = t_sep;
+    if (st_range != FSP_OK) {
+      for (int i = 0; i < 5; ++i) p->var[i] = best[i];
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      return st_range;
+    }
     if (e == hipSuccess && t_fused < t_sep)
       for (int i = 1; i <= 3; ++i) best[i] = fsp::FUSED;
   } else if (times_ms) {

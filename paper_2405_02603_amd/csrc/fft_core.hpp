@@ -323,6 +323,10 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("" ::: "memory");
 }
 
+// Keeps the compiler from moving memory operations across this point, so
+// loads issued before it complete (in order) before those issued after.
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
 // ---------------------------------------------------------------- stages
 // Two consecutive complex values of the twiddle table in one load where the type allows.
 template <typename T>
@@ -337,39 +341,55 @@ __device__ __forceinline__ void load_pair(const cx<T>* p, cx<T>& a, cx<T>& b) {
   }
 }
 
+// The six-power table values of one butterfly (those a radix R needs).
+template <typename T>
+struct TwBase {
+  cx<T> w1, w2, w3, w4, w8, w16;
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void load_twbase(TwBase<T>& t, const cx<T>* __restrict__ tw, int k) {
+  const cx<T>* e = tw + k * TW_PER_K;
+  load_pair(e, t.w1, t.w2);
+  if constexpr (R >= 4) load_pair(e + 4, t.w16, t.w3);
+  if constexpr (R >= 8) load_pair(e + 2, t.w4, t.w8);
+}
+
+// v[r] *= w^(r k) (forward) or its conjugate (inverse), r = 1 .. R-1, from the
+// loaded table values of butterfly k.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void apply_twbase(cx<T>* v, const TwBase<T>& t) {
+  cx<T> w[R];
+  w[1] = t.w1;
+  if constexpr (R >= 3) w[2] = t.w2;
+  if constexpr (R >= 4) w[3] = t.w3;
+  if constexpr (R >= 8) {
+    w[4] = t.w4;
+    w[5] = cmul(t.w4, t.w1);
+    w[6] = cmul(t.w4, t.w2);
+    w[7] = cmul(t.w4, t.w3);
+  }
+  if constexpr (R >= 16) {
+    w[8] = t.w8;
+#pragma unroll
+    for (int r = 9; r < 16; ++r) w[r] = cmul(t.w8, w[r - 8]);
+  }
+  if constexpr (R >= 32) {
+    w[16] = t.w16;
+#pragma unroll
+    for (int r = 17; r < 32; ++r) w[r] = cmul(t.w16, w[r - 16]);
+  }
+#pragma unroll
+  for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
+}
+
 // v[r] *= w^(r k) (forward) or its conjugate (inverse), r = 1 .. R-1.
 template <typename T, int R, int NS, bool INV>
 __device__ __forceinline__ void apply_twiddles(cx<T>* v, const cx<T>* __restrict__ tw, int k) {
   if constexpr (NS > 1) {
-    const cx<T>* e = tw + k * TW_PER_K;
-    cx<T> w[R];
-    cx<T> w1, w2, w3, w4, w8, w16;
-    load_pair(e, w1, w2);
-    w[1] = w1;
-    if constexpr (R >= 3) w[2] = w2;
-    if constexpr (R >= 4) {
-      load_pair(e + 4, w16, w3);
-      w[3] = w3;
-    }
-    if constexpr (R >= 8) {
-      load_pair(e + 2, w4, w8);
-      w[4] = w4;
-      w[5] = cmul(w4, w1);
-      w[6] = cmul(w4, w2);
-      w[7] = cmul(w4, w3);
-    }
-    if constexpr (R >= 16) {
-      w[8] = w8;
-#pragma unroll
-      for (int r = 9; r < 16; ++r) w[r] = cmul(w8, w[r - 8]);
-    }
-    if constexpr (R >= 32) {
-      w[16] = w16;
-#pragma unroll
-      for (int r = 17; r < 32; ++r) w[r] = cmul(w16, w[r - 16]);
-    }
-#pragma unroll
-    for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);
+    TwBase<T> t;
+    load_twbase<T, R>(t, tw, k);
+    apply_twbase<T, R, INV>(v, t);
   }
 }
 
@@ -454,6 +474,40 @@ __device__ __forceinline__ void lds_last_stage(const cx<T>* lds, const cx<T>* __
       stage_twiddles<T, L, PID, REV, S, INV, FULL>(v[j], tw, b);
       Dft<R, INV, T>::run(v[j]);
     }
+  }
+}
+
+// Last stage with the butterflies' table values already loaded (tb[j] for
+// butterfly q + NQ j, a stage that spans the pencil: NS == NB).
+template <typename T, int L, int PID, bool REV, int NQ, bool INV, int J, int R, class IDX>
+__device__ __forceinline__ void lds_last_stage_pre(const cx<T>* lds, const TwBase<T> (&tb)[J], int q, IDX idx,
+                                                   cx<T> (&v)[J][R]) {
+  constexpr int NB = L / R;
+  static_assert(R == plan_radix(L, PID, REV, plan_len(L, PID) - 1), "register array matches the last radix");
+  static_assert(J == (NB + NQ - 1) / NQ, "register array matches the butterfly split");
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int b = q + NQ * j;
+    if ((NB % NQ == 0) || b < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[j][r] = lds[idx(b + r * NB)];
+      apply_twbase<T, R, INV>(v[j], tb[j]);
+      Dft<R, INV, T>::run(v[j]);
+    }
+  }
+}
+
+// Table values of the last stage's butterflies q + NQ j.
+template <typename T, int L, int PID, bool REV, int NQ, int J>
+__device__ __forceinline__ void load_last_twbase(TwBase<T> (&tb)[J], const cx<T>* __restrict__ tw, int q) {
+  constexpr int S = plan_len(L, PID) - 1;
+  constexpr int R = plan_radix(L, PID, REV, S);
+  constexpr int NB = L / R;
+  const cx<T>* tws = tw + tw_base(L, PID, REV) + tw_stage_off(L, PID, REV, S);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int b = q + NQ * j;
+    load_twbase<T, R>(tb[j], tws, (NB % NQ == 0) || b < NB ? b : 0);
   }
 }
 

@@ -160,12 +160,19 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
 }
 
 // ----------------------------------------------------------------- P3
+// Loads are issued in the order they are consumed (twiddles, Green's rows,
+// the first pencil set, the second), so the first transform waits only for
+// its own data while the second set is still arriving.  Two-stage plans load
+// the table values of their forward butterflies once, for both sets.
 // TWF: the plan's complete twiddle table is read into LDS once per block, so
 // the butterflies load every power instead of multiplying it out of six.
 template <typename T, int L, int PID, int TC, int NQ, bool TWF = false>
 __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   constexpr int K = plan_len(L, PID);
   static_assert(!TWF || K > 1, "single-stage plans have no twiddles");
+  constexpr bool PRE = K == 2 && !TWF && sizeof(T) == 4;  // float64 keeps its registers for occupancy
+  constexpr int NT = TC * NQ;
+  constexpr int TWN = TWF ? (twf_size(L, PID) + NT - 1) / NT : 1;  // table entries per thread
   __shared__ cx<T> lds[K > 1 ? L * TC : 1];
   __shared__ cx<T> twl[TWF ? twf_size(L, PID) : 1];
   const int tid = threadIdx.x;
@@ -174,16 +181,25 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   bool cok;
   place_column<TC>(a, c, col, p, cok);
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
-  if constexpr (TWF) {  // before the pencil loads, so waiting for it does not wait for them
-    const cx<T>* src = tw + tw_size(L, PID);
-    for (int e = tid; e < twf_size(L, PID); e += TC * NQ) twl[e] = src[e];
-    tw = twl;  // made visible by the barrier after the first stage's LDS writes
-  }
   const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
   auto idx = [c](int row) { return row * TC + c; };
   using F = FirstStage<L, PID, false, NQ>;   // forward, first stage
   using Lf = LastStage<L, PID, false, NQ>;   // forward, last stage == inverse, first stage
+  using Li = LastStage<L, PID, true, NQ>;    // inverse, last stage
   static_assert(F::R % 2 == 0, "forward plans start with an even radix");
+  static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
+
+  cx<T> twr[TWN];
+  if constexpr (TWF) {
+    const cx<T>* src = tw + tw_size(L, PID);
+#pragma unroll
+    for (int i = 0; i < TWN; ++i) {
+      const int e = tid + NT * i;
+      twr[i] = e < twf_size(L, PID) ? src[e] : czero<T>();
+    }
+  }
+  TwBase<T> tbf[PRE ? Lf::J : 1];
+  if constexpr (PRE) load_last_twbase<T, L, PID, false, NQ>(tbf, tw, q);
 
   // Green's values for the rows this thread holds after the forward transform;
   // the octant is stored in column tiles of TC, so a tile's rows are contiguous.
@@ -203,10 +219,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   }
 
   // k1 = p and its partner 2 n1 - p share the Green's rows; p = 0 and p = n1
-  // have no partner.  Both pencil sets are loaded before either is
-  // transformed, so the second set's loads overlap the first set's work.
-  using Li = LastStage<L, PID, true, NQ>;
-  static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
+  // have no partner.
   const bool two = !(p == 0 || p == a.n1);
   cx<T>* base_a = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)p * a.outer_stride + col;
   cx<T>* base_b = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)(2 * a.n1 - p) * a.outer_stride + col;
@@ -240,11 +253,15 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
         }
       }
     } else {
+      const cx<T>* tws = TWF ? static_cast<const cx<T>*>(twl) : tw;
       write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
       lds_barrier();
-      lds_stages<T, L, PID, false, 1, K - 1, NQ, false, TWF>(lds, tw, q, idx);
+      lds_stages<T, L, PID, false, 1, K - 1, NQ, false, TWF>(lds, tws, q, idx);
       cx<T> w[Lf::J][Lf::R];
-      lds_last_stage<T, L, PID, false, NQ, false, TWF>(lds, tw, q, idx, w);
+      if constexpr (PRE)
+        lds_last_stage_pre<T, L, PID, false, NQ, false>(lds, tbf, q, idx, w);
+      else
+        lds_last_stage<T, L, PID, false, NQ, false, TWF>(lds, tws, q, idx, w);
       // multiply, then the first inverse stage (span 1) in registers
 #pragma unroll
       for (int j = 0; j < Lf::J; ++j) {
@@ -255,9 +272,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       lds_barrier();
       write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, w, q, idx);
       lds_barrier();
-      lds_stages<T, L, PID, true, 1, K - 1, NQ, true, TWF>(lds, tw, q, idx);
+      lds_stages<T, L, PID, true, 1, K - 1, NQ, true, TWF>(lds, tws, q, idx);
       cx<T> u[Li::J][Li::R];
-      lds_last_stage<T, L, PID, true, NQ, true, TWF>(lds, tw, q, idx, u);
+      lds_last_stage<T, L, PID, true, NQ, true, TWF>(lds, tws, q, idx, u);
 #pragma unroll
       for (int j = 0; j < Li::J; ++j) {
         const int b = q + NQ * j;
@@ -269,8 +286,18 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
     }
   };
   cx<T> raw_a[F::J][F::R / 2], raw_b[F::J][F::R / 2];
+  issue_fence();
   load_set(base_a, true, raw_a);
+  issue_fence();
   load_set(base_b, two, raw_b);
+  issue_fence();
+  if constexpr (TWF) {  // the table arrived before the pencils; visible after the first barrier
+#pragma unroll
+    for (int i = 0; i < TWN; ++i) {
+      const int e = tid + NT * i;
+      if (e < twf_size(L, PID)) twl[e] = twr[i];
+    }
+  }
   run_set(base_a, raw_a);
   if (two) {
     lds_barrier();

@@ -332,10 +332,12 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
   };
   hipError_t e = hipSuccess;
   if (g.var[1] == FUSED) {
-    // passes 1-3 as one fused kernel over column tiles
-    if (first > 1 || last < 3) return hipErrorInvalidValue;
+    // passes 1-3 as one fused kernel over column tiles: a range holds all of
+    // them or none (pass 0 or pass 4 alone)
+    const bool mid = first <= 3 && last >= 1;
+    if (mid && (first > 1 || last < 3)) return hipErrorInvalidValue;
     if (first == 0) e = run(0, 0, ncols);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !mid) return e == hipSuccess && last == 4 ? run(4, 0, ncols) : e;
     SlabArgs sa{};
     for (int i = 0; i < g.items; ++i) {
       sa.data[i] = g.work[i];

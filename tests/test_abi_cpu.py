@@ -148,6 +148,12 @@ def test_schedule_validation(lib):
     assert lib.fsp_plan_set_schedule(h, ok) == _lib.FSP_OK
     fused = (ctypes.c_int * 5)(0, 3, 3, 3, 0)
     assert lib.fsp_plan_set_schedule(h, fused) == _lib.FSP_OK
+    # with the fused schedule a pass range holds all of passes 1-3 or none of them
+    dummy = ctypes.c_void_p(256)
+    for first, last in ((1, 1), (2, 2), (2, 4), (0, 2), (3, 4)):
+        assert lib.fsp_solve_passes(h, dummy, dummy, first, last, None) == _lib.FSP_ERR_INVALID_ARG, (first, last)
+    for first, last in ((0, 0), (4, 4), (1, 3), (0, 4)):
+        assert lib.fsp_solve_passes(h, dummy, dummy, first, last, None) == _lib.FSP_ERR_NOT_READY, (first, last)
     for bad in ((0, 3, 0, 3, 0), (3, 0, 0, 0, 0), (0, 0, 0, 0, 4), (-1, 0, 0, 0, 0)):
         assert lib.fsp_plan_set_schedule(h, (ctypes.c_int * 5)(*bad)) == _lib.FSP_ERR_INVALID_ARG
     lib.fsp_plan_destroy(h)

@@ -198,3 +198,31 @@ def test_fused_schedule_in_batch_and_anisotropic_n2(torch_cuda):
     torch.cuda.synchronize()
     for o, r in zip(outs, refs):
         assert rel_l2(to_host(o), r) <= F32_TOL
+
+
+@pytest.mark.parametrize("prec,n", [("f32", 32), ("f32", 64), ("f64", 32), ("f64", 48)])
+def test_autotune_fused_sizes(torch_cuda, prec, n):
+    """On grids small enough for the fused schedule the autotuner also times passes 1-3
+    fused against the best separate ones (pass 0 and pass 4 are then run on their own);
+    whatever it keeps matches the oracle, and so does a solve split into pass ranges."""
+    from paper_2405_02603_amd import _lib
+    torch = torch_cuda
+    lo, hi = (-1.0,) * 3, (1.0,) * 3
+    rho = W.source_density(n, lo, hi, W.multiblob(5))
+    ref = reference(rho, "vico_dct", lo, hi, use_direct=False)
+    tol = F64_TOL if prec == "f64" else F32_TOL
+    dt = torch.float64 if prec == "f64" else torch.float32
+    plan = _plan(n, lo, hi, "vico_dct", prec)
+    r = to_dev(rho, dt)
+    times = plan.autotune(r, reps=2)
+    torch.cuda.synchronize()
+    assert times["fused_1_3"] > 0 and times["separate_1_3"] > 0
+    assert (plan.schedule[1] == _lib.FUSED) == (times["fused_1_3"] < times["separate_1_3"])
+    assert rel_l2(to_host(plan.solve(r)), ref) <= tol
+    plan.schedule = [0, _lib.FUSED, _lib.FUSED, _lib.FUSED, 0]
+    phi = torch.empty_like(r)
+    plan.solve_passes(r, None, 0, 0)
+    plan.solve_passes(None, None, 1, 3)
+    plan.solve_passes(None, phi, 4, 4)
+    torch.cuda.synchronize()
+    assert rel_l2(to_host(phi), ref) <= tol
