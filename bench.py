@@ -44,6 +44,43 @@ def pass_bytes(n, rb):
     return [real + half1, half1 + half2, 2 * half2 + octant, half2 + half1, half1 + real]
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vico_dct_256.txt")
+
+
+def source_digest():
+    """Digest of the HIP sources (file names and contents); a counter summary
+    taken from other sources no longer describes these kernels."""
+    import hashlib
+
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2405_02603_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(greens, n, prec, pass_idx, variant):
+    """HBM bytes per launch (reads + writes, counter readings scaled by the copy
+    calibration) of one pass kernel, from the committed rocprofv3 summary; None
+    when the summary has no such entry or was taken from other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            lines = [ln.split() for ln in fh if ln.strip() and not ln.startswith("#")]
+    except OSError:
+        return None
+    src = [ln[1] for ln in lines if ln[0] == "source"]
+    if not src or src[0] != source_digest():
+        return None
+    key = [greens, str(n), prec, f"P{pass_idx + 1}", f"v{variant}"]
+    for ln in lines:
+        if ln[0] == "traffic" and ln[1:6] == key:
+            return int(ln[6])
+    return None
+
+
 def parse(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,14 +91,15 @@ def parse(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+                    help="kept for older command lines: the 1 GiB device copy (counter calibration for "
+                         "rocprofv3 --pmc) now always runs")
     ap.add_argument("--skip-f64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
     ap.add_argument("--workload", default="single", choices=["single", "batch", "serve"],
                     help="single: the 256^3 headline; batch: 64 uneven right-hand sides per graph launch; "
                          "serve: Poisson-arrival serving loop")
     ap.add_argument("--batch-count", type=int, default=64)
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -77,6 +115,34 @@ def time_solves(torch, plan, rho, phi, steps, warmup):
         plan.solve(rho, phi)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def solve_percentiles(torch, plan, rho, phi, reps):
+    """p10 / p50 / p90 of single-solve times (HIP events around each solve), ms."""
+    import numpy as np
+
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        plan.solve(rho, phi, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"p10_ms": round(float(np.percentile(t, 10)), 5), "p50_ms": round(float(np.percentile(t, 50)), 5),
+            "p90_ms": round(float(np.percentile(t, 90)), 5), "reps": reps}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def time_passes(torch, plan, rho, phi, steps):
@@ -135,9 +201,31 @@ def cpu_baseline(rho64, lo, hi, greens_kind, seconds):
         el = time.perf_counter() - t0
         if el >= seconds or count >= 50:
             break
-    return ref, {"value": count / el, "unit": "solves/s", "cores": cores, "kind": "oracle",
-                 "sample": f"{count} float64 FFT-route solves of the same {n[0]}^3 workload "
-                           f"(scipy.fft, workers={cores}), {el:.1f} s; kernel table excluded"}
+    out = {"value": count / el, "unit": "solves/s", "cores": cores, "kind": "oracle",
+           "sample": f"{count} float64 FFT-route solves of the same {n[0]}^3 workload "
+                     f"(scipy.fft, workers={cores}), {el:.1f} s; kernel table excluded",
+           "cpu": cpu_model()}
+    out["direct_sum_32"] = direct_sum_timing()
+    return ref, out
+
+
+def direct_sum_timing():
+    """The oracle's literal O(N^6) sum at 32^3 on one thread (informational)."""
+    import workloads as W
+    from oracle import direct, greens
+
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:
+        return None
+    n, lo, hi = (32, 32, 32), (-0.5,) * 3, (0.5,) * 3
+    rho = W.source_density(n, lo, hi, W.centred_gaussian(0.05))
+    k = greens.hockney_octant(n, lo, hi)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        direct.convolve(rho, k, greens.spacing(n, lo, hi))
+        el = time.perf_counter() - t0
+    return {"seconds": round(el, 3), "threads": 1, "grid": "32^3 Hockney-Eastwood"}
 
 
 def bench_batch(args):
@@ -151,11 +239,16 @@ def bench_batch(args):
     items = W.batch_mix(seed=4, count=args.batch_count)
     src = {}
     plans, rhos, host = [], [], []
+    tuned = {}
     for it in items:
         p = Plan(n=it.n, lo=it.lo, hi=it.hi, greens="vico_dct", prec="f32", precompute=False)
         if it.n not in src:
             p.precompute()
             src[it.n] = p
+            if not args.no_autotune:   # later plans of this grid start with the tuned schedule
+                r0 = torch.from_numpy(W.source_density(it.n, it.lo, it.hi, it.source)).to("cuda", torch.float32)
+                p.autotune(r0, torch.empty_like(r0), reps=4)
+                tuned[it.n] = p.schedule
         else:
             p.share_ghat(src[it.n])
         r = W.source_density(it.n, it.lo, it.hi, it.source)
@@ -201,6 +294,7 @@ def bench_batch(args):
         "model_bytes_per_step": model,
         "fp64_single_solves": {"solves_per_s": round(len(items) * 1e3 / ms64, 1), "ms_per_batch": round(ms64, 4)},
         "max_rel_l2_f32_vs_gpu_f64": err,
+        "schedules": {str(k): v for k, v in sorted(tuned.items())},
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -290,6 +384,7 @@ def main(argv=None):
             tune = plan.autotune(rho, phi, reps=4)   # outside the timed region
         torch.cuda.synchronize()
         ms = time_solves(torch, plan, rho, phi, args.steps, args.warmup)
+        pct = solve_percentiles(torch, plan, rho, phi, args.steps)
         pass_ms = time_passes(torch, plan, rho, phi, args.steps)
         plan.solve(rho, phi)
         torch.cuda.synchronize()
@@ -299,6 +394,7 @@ def main(argv=None):
             "model_bytes": plan.model_bytes,
             "hbm_frac_model": plan.model_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
             "pass_ms": pass_ms,
+            "percentiles": pct,
             "phi": phi.double().cpu().numpy(),
             "rb": 4 if prec == "f32" else 8,
             "schedule": plan.schedule,
@@ -308,15 +404,16 @@ def main(argv=None):
         del plan, rho, phi
         torch.cuda.empty_cache()
 
-    if args.copy_calibration:
-        extra["copy_calibration"] = copy_calibration(torch)
+    # a plain device copy of 1 GiB: the bandwidth a streaming kernel reaches on this GPU
+    extra["copy_calibration"] = copy_calibration(torch)
 
     r32 = results["f32"]
     pb = pass_bytes((n, n, n), r32["rb"])
     dom = int(np.argmax(r32["pass_ms"]))
     achieved = pb[dom] / (r32["pass_ms"][dom] * 1e-3) / 1e9
+    traffic = measured_traffic(args.greens, n, "f32", dom, r32["schedule"][dom])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": PASS_NAMES[dom], "bytes_per_launch": pb[dom],
                 "avg_launch_ms": round(r32["pass_ms"][dom], 5)}
 
@@ -343,11 +440,13 @@ def main(argv=None):
         "roofline": roofline,
         "schedule": r32["schedule"],
         "autotune_ms": r32["tune_ms"],
+        "solve_time_percentiles": r32["percentiles"],
     }
     if "f64" in results:
         r64 = results["f64"]
         pb64 = pass_bytes((n, n, n), 8)
         out["fp64"] = {"solves_per_s": round(r64["solves_per_s"], 2), "ms_per_step": round(r64["ms"], 5),
+                       "solve_time_percentiles": r64["percentiles"],
                        "schedule": r64["schedule"], "autotune_ms": r64["tune_ms"],
                        "hbm_frac_model": round(r64["hbm_frac_model"], 4),
                        "passes": [{"kernel": PASS_NAMES[i], "ms": round(r64["pass_ms"][i], 5),

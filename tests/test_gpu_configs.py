@@ -1,0 +1,166 @@
+"""GPU parity at the sizes of the benchmark configurations.
+
+* Convergence (Section 3.1, Table 3): the GPU solve of the centred sigma = 0.05
+  Gaussian on [-0.5, 0.5]^3 against its closed form, Hockney-Eastwood beside
+  both Vico-Greengard precomputes, float64 and float32, plus the off-centre
+  sigma = 0.03 Gaussian.  Each float64 error equals the oracle's to 1e-12 and
+  the orders of magnitude are the paper's.
+* 256^3, both kernels, both precisions, cube [-1,1]^3 and box [-1,1]^2 x [-2,2],
+  8-Gaussian source (seed 3), with the autotuned schedule the benchmark times:
+  the whole result against the float64 oracle (FFT route).
+* 512^3: sampled outputs of the direct sum (Hockney-Eastwood, whose kernel table
+  is closed-form) and, for Vico-Greengard, the closed-form potential on a strided
+  subgrid of the result.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, exact, greens
+
+from gpu_util import kernel_octant, reference, rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-6
+F32_TOL_512 = 2e-6
+UNIT = ((-0.5,) * 3, (0.5,) * 3)
+CUBE = ((-1.0,) * 3, (1.0,) * 3)
+SLAB = ((-1.0, -1.0, -2.0), (1.0, 1.0, 2.0))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _solve(torch, n, box, kind, prec, rho, tune=False):
+    from paper_2405_02603_amd import Plan
+    dt = torch.float64 if prec == "f64" else torch.float32
+    plan = Plan(n=n, lo=box[0], hi=box[1], greens=kind, prec=prec)
+    r = to_dev(rho, dt)
+    phi = torch.empty_like(r)
+    if tune:
+        plan.autotune(r, phi, reps=2)
+    plan.solve(r, phi)
+    torch.cuda.synchronize()
+    out = to_host(phi)
+    plan.close()
+    del r, phi
+    torch.cuda.empty_cache()
+    return out
+
+
+def _paper_rows(golden_dir):
+    rows = {}
+    with open(f"{golden_dir}/accuracy_table.txt") as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                m, acc, n = line.split()
+                rows[(m, int(n))] = float(acc)
+    return rows
+
+
+def test_convergence_table(torch_cuda, golden_dir):
+    """Centred Gaussian, sigma = 0.05, unit cube: GPU float64 errors against the closed form."""
+    src = W.centred_gaussian(0.05)
+    rows = _paper_rows(golden_dir)
+    err = {}
+    for kind in ("hockney", "vico", "vico_dct"):
+        for n in (16, 32, 64, 128):
+            if kind == "vico" and n > 64:
+                continue  # the (4n)^3 route is checked against the DCT route below
+            rho = W.source_density(n, *UNIT, src)
+            phi = _solve(torch_cuda, n, UNIT, kind, "f64", rho)
+            if n <= 64:   # the GPU result is the oracle's
+                assert rel_l2(phi, reference(rho, kind, *UNIT, use_direct=False)) <= F64_TOL, (kind, n)
+            err[(kind, n)] = rel_l2(phi, exact.source_potential(n, *UNIT, src))
+            if (kind, n) in rows:
+                acc = rows[(kind, n)]
+                assert acc / 10 <= err[(kind, n)] <= acc * 10, (kind, n, err[(kind, n)])
+    # Hockney-Eastwood: second order (Section 2.2)
+    for n in (16, 32, 64):
+        order = np.log2(err[("hockney", n)] / err[("hockney", 2 * n)])
+        assert 1.8 <= order <= 2.2, (n, order)
+    # Vico-Greengard: spectral; both precomputes give the same solve
+    assert err[("vico_dct", 64)] < 1e-13 and err[("vico_dct", 128)] < 1e-13
+    for n in (16, 32, 64):
+        assert abs(err[("vico", n)] - err[("vico_dct", n)]) <= 1e-12 + 1e-9 * err[("vico_dct", n)]
+    print("convergence", {f"{k}_{n}": f"{e:.3e}" for (k, n), e in sorted(err.items())})
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_offcentre_gaussian_f64_and_f32(torch_cuda, n):
+    """sigma = 0.03 Gaussian at (0.1, -0.2, 0.15): float64 equals the oracle, float32 within its
+    bound of it; Vico-Greengard reaches the closed form to ~1e-12 at 64^3 and rounding at 128^3."""
+    src = W.offcentre_gaussian()
+    rho = W.source_density(n, *UNIT, src)
+    closed = exact.source_potential(n, *UNIT, src)
+    for kind in ("hockney", "vico_dct"):
+        ref = reference(rho, kind, *UNIT, use_direct=False)
+        p64 = _solve(torch_cuda, n, UNIT, kind, "f64", rho)
+        p32 = _solve(torch_cuda, n, UNIT, kind, "f32", rho)
+        assert rel_l2(p64, ref) <= F64_TOL
+        assert rel_l2(p32, ref) <= F32_TOL
+        e = rel_l2(p64, closed)
+        if kind == "vico_dct":
+            assert e <= (1e-10 if n == 64 else 1e-13), e
+        else:
+            assert 1e-4 < e < 2e-2, e
+
+
+@pytest.mark.parametrize("kind", ["hockney", "vico_dct"])
+@pytest.mark.parametrize("box", [CUBE, SLAB], ids=["cube", "slab"])
+def test_full_size_256(torch_cuda, kind, box):
+    """256^3, 8-Gaussian source: whole result against the float64 oracle, both precisions,
+    autotuned schedule (as timed by the benchmark)."""
+    n = 256
+    src = W.multiblob(seed=3, count=8)
+    rho = W.source_density(n, *box, src)
+    ref = reference(rho, kind, *box, use_direct=False)
+    e64 = rel_l2(_solve(torch_cuda, n, box, kind, "f64", rho, tune=True), ref)
+    e32 = rel_l2(_solve(torch_cuda, n, box, kind, "f32", rho, tune=True), ref)
+    print("full 256", kind, box[1], f"f64 {e64:.3e} f32 {e32:.3e}")
+    assert e64 <= F64_TOL
+    assert e32 <= F32_TOL
+
+
+def _strided_closed_form(n, box, src, s):
+    """Closed-form potential at the cell centres with indices s k (k < n / s): the same
+    centres form a grid of n / s cells of width s h starting half a cell earlier."""
+    lo, hi = np.asarray(box[0], float), np.asarray(box[1], float)
+    h = (hi - lo) / n
+    lo2 = lo + 0.5 * h * (1 - s)
+    return exact.source_potential(n // s, tuple(lo2), tuple(lo2 + n * h), src)
+
+
+@pytest.mark.parametrize("box", [CUBE, SLAB], ids=["cube", "slab"])
+def test_full_size_512(torch_cuda, box):
+    """512^3: Hockney-Eastwood against the direct sum at sampled outputs; Vico-Greengard against
+    the closed form on every 4th point per axis (the closed-form floor of this source in this
+    box is ~1e-9: a little of the widest blobs' mass lies outside the box)."""
+    n = 512
+    src = W.multiblob(seed=3, count=8)
+    rho = W.source_density(n, *box, src)
+    h = greens.spacing((n,) * 3, *box)
+    rng = np.random.default_rng(11)
+    pts = [tuple(int(v) for v in rng.integers(0, n, size=3)) for _ in range(5)]
+    pts += [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, n // 3, n - 1)]
+    k_he = kernel_octant("hockney", (n,) * 3, *box)
+    want = direct.convolve_at(rho, k_he, h, pts)
+    del k_he
+    scale = float(np.max(np.abs(want)))
+    closed = _strided_closed_form(n, box, src, 4)
+    for prec, tol_pt, tol_cf in (("f64", 1e-12, 1e-8), ("f32", 1e-6, F32_TOL_512 + 1e-8)):
+        phi = _solve(torch_cuda, n, box, "hockney", prec, rho)
+        got = np.array([phi[p] for p in pts])
+        assert np.max(np.abs(got - want)) <= tol_pt * scale, (prec, got, want)
+        del phi
+        phi = _solve(torch_cuda, n, box, "vico_dct", prec, rho)
+        e = rel_l2(phi[::4, ::4, ::4], closed)
+        print("full 512", box[1], prec, f"vico vs closed form {e:.3e}")
+        assert e <= tol_cf, (prec, e)
+        del phi
