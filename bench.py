@@ -343,6 +343,7 @@ def bench_serve(args):
         "p50_ms": round(rep["p50_ms"], 3), "p99_ms": round(rep["p99_ms"], 3), "requests": rep["requests"],
         "rejected": rep["rejected"], "launches": rep["launches"], "peak_bytes": rep["peak_bytes"],
         "spot_checks": rep["spot_checks"], "spot_rel_l2_max": rep["spot_rel_l2_max"],
+        "seen_lag_ms": rep["seen_lag_ms"],
         "saturation_sweep": sweep,
     }
     print(json.dumps(out), flush=True)

@@ -41,6 +41,7 @@ class Job:
     nbytes: int = 0              # filled by the executor's sizing callback
     t_admit: Optional[float] = None
     t_done: Optional[float] = None
+    t_seen: Optional[float] = None   # host clock when the completion was observed
     status: str = "queued"       # queued | running | done | rejected | cancelled | failed
     error: Optional[str] = None
     spot_rel_l2: Optional[float] = None
@@ -210,9 +211,16 @@ class GpuExecutor:
 
     # -------------------------------------------------------------- clock
     def start_clock(self) -> float:
+        """Zero of both clocks.  An event recorded on an idle stream may carry the
+        time stamp of that stream's last finished command, so a tiny kernel runs
+        right before the start event to give it the current time."""
         torch = self.torch
+        torch.cuda.synchronize(self.device)
+        stream = torch.cuda.current_stream(self.device)
         self.t0_event = torch.cuda.Event(enable_timing=True)
-        self.t0_event.record(torch.cuda.current_stream(self.device))
+        tick = torch.zeros(1, device=self.device)
+        tick.add_(1.0)
+        self.t0_event.record(stream)
         torch.cuda.synchronize(self.device)
         self.t0_wall = time.perf_counter()
         return self.t0_wall
@@ -299,7 +307,9 @@ class Server:
                 j.t_arrival *= time_scale
                 self.sched.submit(j)
             for slot, t in self.ex.poll():
-                self.sched.complete(slot, t)
+                seen = self.ex.now()
+                for j in self.sched.complete(slot, t):
+                    j.t_seen = seen
             for slot, group in self.sched.admit(now):
                 self.ex.launch(slot, group)
                 launches += 1
@@ -316,6 +326,9 @@ class Server:
         lat = [(j.t_done - j.t_arrival) * 1e3 for j in done]
         span = (max(j.t_done for j in done) - min(j.t_arrival for j in done)) if done else float("nan")
         spots = [j.spot_rel_l2 for j in done if j.spot_rel_l2 is not None]
+        # host time at which a completion was seen minus its device time: small and
+        # non-negative when the two clocks share their zero
+        seen_lag = [(j.t_seen - j.t_done) * 1e3 for j in done if j.t_seen is not None]
         return {
             "requests": len(self.jobs),
             "done": len(done),
@@ -329,4 +342,6 @@ class Server:
             "budget_bytes": self.sched.budget,
             "spot_checks": len(spots),
             "spot_rel_l2_max": max(spots) if spots else None,
+            "seen_lag_ms": {"min": min(seen_lag), "p50": percentile(seen_lag, 50),
+                            "max": max(seen_lag)} if seen_lag else None,
         }

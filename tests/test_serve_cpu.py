@@ -1,11 +1,12 @@
 """Admission rules of the serving scheduler (no GPU): budget, FIFO order,
-folding of equal shapes, cancellation, and a simulated run in which the bytes
-in flight never exceed the budget."""
+folding of equal shapes, cancellation, a simulated run in which the bytes
+in flight never exceed the budget, and the serving loop on the host clock."""
 import random
+import time
 
 import pytest
 
-from paper_2405_02603_amd.serve import Job, Scheduler, percentile, request_bytes
+from paper_2405_02603_amd.serve import Job, Scheduler, Server, percentile, request_bytes
 
 
 def _job(rid, n=32, greens="vico_dct", nbytes=100, spot=False, t=0.0):
@@ -100,3 +101,48 @@ def test_failed_launch_frees_bytes():
 def test_percentile():
     assert percentile([1, 2, 3, 4], 50) == pytest.approx(2.5)
     assert percentile([5], 99) == 5
+
+
+class _HostExecutor:
+    """Executor stand-in on the host clock: a launch finishes ``service`` seconds later."""
+
+    def __init__(self, service=0.002):
+        self.service = service
+        self.inflight = {}
+        self.t0 = None
+
+    def size_job(self, job):
+        job.nbytes = 1 << 20
+
+    def start_clock(self):
+        self.t0 = time.perf_counter()
+        return self.t0
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def launch(self, slot, group):
+        self.inflight[slot] = self.now() + self.service
+
+    def poll(self):
+        now = self.now()
+        out = [(s, t) for s, t in self.inflight.items() if t <= now]
+        for s, _ in out:
+            del self.inflight[s]
+        return out
+
+
+def test_server_loop_on_host_clock():
+    """The serving loop end to end: every request completes no earlier than its arrival plus the
+    service time, completions are seen after they happen, and the budget and slots hold."""
+    ex = _HostExecutor(service=0.002)
+    srv = Server(ex, budget_bytes=3 << 20, slots=2)
+    jobs = [_job(i, n=32, t=0.004 * i + (0.001 if i % 3 else 0.0)) for i in range(40)]
+    rep = srv.run(jobs)
+    assert rep["done"] == 40 and rep["rejected"] == 0
+    assert rep["peak_bytes"] <= 3 << 20
+    for j in jobs:
+        assert j.t_done - j.t_arrival >= 0.002 - 1e-9
+        assert j.t_seen >= j.t_done
+    assert rep["seen_lag_ms"]["min"] >= 0.0
+    assert rep["p99_ms"] >= rep["p50_ms"] >= 2.0
