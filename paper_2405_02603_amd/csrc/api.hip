@@ -165,6 +165,7 @@ struct fsp_plan_s {
   int gtile = 0;  // column tile of the blocked Green's octant
   long long plane = 0;  // complex elements between S planes i0
   int chunks = 1;       // column chunks for passes 1-3
+  int gather_min = fsp::CONV_GATHER_MIN_BLOCKS;  // axis-0 grid size from which the lone column is gathered
   size_t tw_row_off[fsp::NUM_PLANS]{}, tw_c1_off[fsp::NUM_PLANS]{}, tw_c0_off[fsp::NUM_PLANS]{}, oct_off = 0;
   int var[5]{};  // schedule variant of each pass
   size_t ghat_bytes = 0, work_bytes = 0, pre_bytes = 0;
@@ -310,6 +311,7 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     if (const char* e = std::getenv("FSP_PLANE_PAD")) pad = std::atoll(e);
     p->plane = 2LL * p->n[1] * p->pitch + pad;
     if (const char* e = std::getenv("FSP_CHUNKS")) p->chunks = std::max(1, std::atoi(e));
+    if (const char* e = std::getenv("FSP_CONV_GATHER_MIN")) p->gather_min = std::max(0, std::atoi(e));
   }
   p->work_bytes = align_up((size_t)p->n[0] * p->plane * cb, 256);
   {
@@ -548,6 +550,7 @@ static fsp::SolveGeom group_geom(const fsp_plan_s* p) {
   g.pitch = p->pitch;
   g.plane = p->plane;
   g.chunks = p->chunks;
+  g.gather_min = p->gather_min;
   const char* gb = static_cast<const char*>(p->ghat_read);
   for (int i = 0; i < 5; ++i) g.var[i] = p->var[i];
   const int pr1 = fsp::row_cfg<float>(p->n[2], p->var[0]).pid, pr5 = fsp::row_cfg<float>(p->n[2], p->var[4]).pid;
@@ -576,7 +579,8 @@ static void add_item(fsp::SolveGeom& g, const fsp_plan_s* p, const void* rho, vo
 
 static bool same_shape(const fsp_plan_s* a, const fsp_plan_s* b) {
   bool same = a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] && a->d.prec == b->d.prec &&
-              a->pitch == b->pitch && a->plane == b->plane && a->chunks == b->chunks;
+              a->pitch == b->pitch && a->plane == b->plane && a->chunks == b->chunks &&
+              a->gather_min == b->gather_min;
   for (int i = 0; i < 5; ++i) same = same && a->var[i] == b->var[i];
   return same;
 }

@@ -48,6 +48,8 @@ struct ColArgs {
   int nouter;                 // outer indices (P2/P4: n0; P3: n1 + 1 pairs)
   int n1;                     // P3: n1 (pairs k1 and 2 n1 - k1 share a Green's row)
   long long g_k1_stride;      // P3: reals between Green's blocks k1 (tiles (n0+1) TC)
+  int ntail;                  // P3: leading blocks that gather column ncols - 1 over TC k1 pairs
+  int gather_min;             // P3 (host side): grid size from which the launcher gathers
 };
 
 struct RowArgs {
@@ -179,7 +181,22 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   const int c = tid % TC, q = tid / TC;
   int col, p;  // p: k1 in [0, n1]; the thread also handles 2 n1 - p
   bool cok;
-  place_column<TC>(a, c, col, p, cok);
+  // The first ntail blocks take the last column (when it is the only column
+  // of its tile) for TC pairs k1 each, so no block transforms a tile that is
+  // mostly empty; their lanes differ in k1, the other blocks' lanes in column.
+  const bool gathered = (int)blockIdx.x < a.ntail;
+  if (gathered) {
+    p = (int)blockIdx.x * TC + c;
+    col = a.ncols - 1;
+    cok = p <= a.n1;
+    if (!cok) p = 0;  // addresses stay in range; nothing is loaded or stored
+  } else {
+    const int bid = (int)blockIdx.x - a.ntail;
+    const int tile = bid % a.ntiles;
+    p = bid / a.ntiles;
+    col = a.col0 + tile * TC + c;
+    cok = col < a.ncols;
+  }
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
   auto idx = [c](int row) { return row * TC + c; };
@@ -219,8 +236,8 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   }
 
   // k1 = p and its partner 2 n1 - p share the Green's rows; p = 0 and p = n1
-  // have no partner.
-  const bool two = !(p == 0 || p == a.n1);
+  // have no partner (uniform in a block unless the block is gathered).
+  const bool two = cok && !(p == 0 || p == a.n1);
   cx<T>* base_a = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)p * a.outer_stride + col;
   cx<T>* base_b = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)(2 * a.n1 - p) * a.outer_stride + col;
   auto load_set = [&](const cx<T>* base, bool on, cx<T> (&raw)[F::J][F::R / 2]) {
@@ -232,7 +249,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? base[(b + r * F::NB) * rs] : czero<T>();
     }
   };
-  auto run_set = [&](cx<T>* base, const cx<T> (&raw)[F::J][F::R / 2]) {
+  auto run_set = [&](cx<T>* base, const cx<T> (&raw)[F::J][F::R / 2], bool st) {
     cx<T> v[F::J][F::R];
 #pragma unroll
     for (int j = 0; j < F::J; ++j) {
@@ -244,7 +261,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
 #pragma unroll
       for (int j = 0; j < F::J; ++j) {
         const int b = q + NQ * j;
-        if (cok && ((F::NB % NQ == 0) || b < F::NB)) {
+        if (st && ((F::NB % NQ == 0) || b < F::NB)) {
 #pragma unroll
           for (int m = 0; m < F::R; ++m) v[j][m] = cscale(v[j][m], gv[j][m]);
           Dft<F::R, true, T>::run(v[j]);
@@ -278,7 +295,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
 #pragma unroll
       for (int j = 0; j < Li::J; ++j) {
         const int b = q + NQ * j;
-        if (cok && ((Li::NB % NQ == 0) || b < Li::NB)) {
+        if (st && ((Li::NB % NQ == 0) || b < Li::NB)) {
 #pragma unroll
           for (int m = 0; m < Li::R / 2; ++m) put<T, PASS_CONV>(&base[(b + m * Li::NB) * rs], u[j][m]);
         }
@@ -298,10 +315,10 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       if (e < twf_size(L, PID)) twl[e] = twr[i];
     }
   }
-  run_set(base_a, raw_a);
-  if (two) {
+  run_set(base_a, raw_a, cok);
+  if (gathered || two) {  // block-uniform: barriers inside
     lds_barrier();
-    run_set(base_b, raw_b);
+    run_set(base_b, raw_b, two);
   }
 }
 

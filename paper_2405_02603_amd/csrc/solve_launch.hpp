@@ -83,6 +83,7 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
 // pipelined persistent kernel (grid of at most CONV_PIPE_BLOCKS blocks) with
 // the shape of variant 1.
 constexpr int CONV_PIPE_BLOCKS = 1024;
+constexpr int CONV_GATHER_MIN_BLOCKS = 2048;
 constexpr int CONV_TWF_LDS = 81920;
 
 template <typename T>
@@ -154,6 +155,24 @@ int col_tiles(int L) {
   return col_tc<T>(L);
 }
 
+// Axis-0 launch geometry: when the last column is alone in its tile it is
+// gathered over TC pairs k1 per block (ntail leading blocks) instead of
+// filling one mostly empty tile per pair.  The gathered blocks read scattered
+// rows and run longer than the others, so this pays only on grids of at least
+// a.gather_min full-tile blocks.
+inline ColArgs conv_gather(const ColArgs& a, int tc) {
+  ColArgs b = a;
+  const int span = a.ncols - a.col0;
+  if (tc > 1 && span % tc == 1 && (long long)a.nouter * (span / tc) >= a.gather_min) {
+    b.ntiles = span / tc;
+    b.ntail = (a.nouter + tc - 1) / tc;
+  } else {
+    b.ntiles = (span + tc - 1) / tc;
+    b.ntail = 0;
+  }
+  return b;
+}
+
 // kind: 0 forward (P2), 1 inverse (P4), 2 forward-multiply-inverse (P3)
 template <typename T>
 hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipStream_t s) {
@@ -162,18 +181,25 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
   if (L == LV && v == VV) {                                                                         \
     constexpr TileCfg c = col_cfg<T>(LV, VV);                                                       \
     constexpr TileCfg cc = conv_cfg<T>(LV, VV);                                                     \
+    static_assert(cc.tiles == col_tc<T>(LV), "the Green octant is blocked by col_tc columns");     \
     const dim3 grid((unsigned)(a.nouter * a.ntiles), (unsigned)items);                              \
     const dim3 block(c.tiles * c.nq);                                                               \
     if (kind == 2) {                                                                                \
-      if constexpr (conv_twf<T>(LV, VV)) {                                                          \
-        hipLaunchKernelGGL((k_col_conv<T, LV, cc.pid, cc.tiles, cc.nq, true>), grid,                \
-                           dim3(cc.tiles * cc.nq), 0, s, a);                                        \
-      } else if constexpr (conv_pipelined<T>(LV, VV)) {                                             \
-        const int nb = a.nouter * a.ntiles < CONV_PIPE_BLOCKS ? a.nouter * a.ntiles : CONV_PIPE_BLOCKS; \
+      if constexpr (conv_pipelined<T>(LV, VV)) {                                                    \
+        ColArgs b = a;                                                                              \
+        b.ntail = 0;                                                                                \
+        const int nb = b.nouter * b.ntiles < CONV_PIPE_BLOCKS ? b.nouter * b.ntiles : CONV_PIPE_BLOCKS; \
         hipLaunchKernelGGL((k_col_conv_pipe<T, LV, cc.pid, cc.tiles, cc.nq>), dim3(nb, items),      \
-                           dim3(cc.tiles * cc.nq), 0, s, a);                                        \
+                           dim3(cc.tiles * cc.nq), 0, s, b);                                        \
       } else {                                                                                      \
-        hipLaunchKernelGGL((k_col_conv<T, LV, c.pid, c.tiles, c.nq>), grid, block, 0, s, a);        \
+        const ColArgs b = conv_gather(a, cc.tiles);                                                 \
+        const dim3 gridc((unsigned)(b.nouter * b.ntiles + b.ntail), (unsigned)items);               \
+        if constexpr (conv_twf<T>(LV, VV))                                                          \
+          hipLaunchKernelGGL((k_col_conv<T, LV, cc.pid, cc.tiles, cc.nq, true>), gridc,             \
+                             dim3(cc.tiles * cc.nq), 0, s, b);                                      \
+        else                                                                                        \
+          hipLaunchKernelGGL((k_col_conv<T, LV, cc.pid, cc.tiles, cc.nq>), gridc,                   \
+                             dim3(cc.tiles * cc.nq), 0, s, b);                                      \
       }                                                                                             \
     } else if (kind == 1)                                                                           \
       hipLaunchKernelGGL((k_col_fft<T, LV, c.pid, c.tiles, c.nq, true>), grid, block, 0, s, a);     \
@@ -249,6 +275,7 @@ struct SolveGeom {
   int pitch;                 // P
   long long plane;           // complex elements between S planes i0 (>= 2 n1 P)
   int chunks;                // column chunks for passes 1-3 (1: whole passes)
+  int gather_min;            // axis-0 blocks from which the lone last column is gathered
   int var[5];                // schedule variant of each pass
   const void* tw_row[5];     // twiddles of length n2 (+ split table) for the plan of P1 / P5
   const void* tw_c1[5];      // twiddles of length 2 n1 for the plan of P2 / P4
@@ -290,6 +317,7 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
   cc.nouter = g.n1 + 1;
   cc.tw = g.tw_c0;
   cc.n1 = g.n1;
+  cc.gather_min = g.gather_min;
   {
     const long long t0 = col_tiles<T>(2 * g.n0);
     cc.g_k1_stride = (g.n2 + 1 + t0 - 1) / t0 * (g.n0 + 1) * t0;

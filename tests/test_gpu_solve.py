@@ -226,3 +226,25 @@ def test_autotune_fused_sizes(torch_cuda, prec, n):
     plan.solve_passes(None, phi, 4, 4)
     torch.cuda.synchronize()
     assert rel_l2(to_host(phi), ref) <= tol
+
+
+@pytest.mark.parametrize("chunks,gather", [("3", "0"), ("1", "0"), ("3", "2048")])
+@pytest.mark.parametrize("prec,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_column_chunks_and_gathered_column(torch_cuda, prec, tol, chunks, gather, monkeypatch):
+    """Passes 1-3 chunk by chunk over the columns (FSP_CHUNKS at plan creation) and the axis-0
+    pass gathering the lone Nyquist column over k1 pairs at any grid size
+    (FSP_CONV_GATHER_MIN=0), for every variant."""
+    torch = torch_cuda
+    monkeypatch.setenv("FSP_CHUNKS", chunks)
+    monkeypatch.setenv("FSP_CONV_GATHER_MIN", gather)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    for n in (16, 32, 64, (48, 64, 96), (96, 32, 128)):
+        n3 = W._as3(n, int)
+        lo, hi = (-1.0,) * 3, (1.0,) * 3
+        rho = W.random_field(n3, 21)
+        plan = _plan(n3, lo, hi, "vico_dct", prec)
+        for v in range(3):
+            plan.schedule = [v] * 5
+            phi = plan.solve(to_dev(rho, dt))
+            torch.cuda.synchronize()
+            assert rel_l2(to_host(phi), reference(rho, "vico_dct", lo, hi, use_direct=False)) <= tol, (n, v)
