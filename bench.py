@@ -382,7 +382,7 @@ def main(argv=None):
         phi = torch.empty_like(rho)
         tune = None
         if not args.no_autotune:
-            tune = plan.autotune(rho, phi, reps=4)   # outside the timed region
+            tune = plan.autotune(rho, phi, reps=8)   # outside the timed region
         torch.cuda.synchronize()
         ms = time_solves(torch, plan, rho, phi, args.steps, args.warmup)
         pct = solve_percentiles(torch, plan, rho, phi, args.steps)

@@ -149,7 +149,7 @@ fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants /* [5] */);
  * fastest per pass in the plan and in the process-wide table used by new
  * plans of this grid and precision.  rho and phi are as in fsp_solve; on
  * return phi holds the solve of rho with the tuned schedule.  Synchronises
- * `stream`.  times_ms (NULL or [5 * 3 + 2]) receives the average time of each
+ * `stream`.  times_ms (NULL or [5 * 3 + 2]) receives the median time of each
  * variant, times_ms[pass * 3 + variant], then the time of passes 1-3 fused and
  * of passes 1-3 with the best separate variants (0 when fusion is not
  * supported); the fused schedule is kept when it is faster.  If a solve fails

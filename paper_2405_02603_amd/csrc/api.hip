@@ -1,6 +1,8 @@
 // api.hip -- plans, buffers, precompute driver and the C ABI declared in fsp.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -694,6 +696,12 @@ fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants) {
   return FSP_OK;
 }
 
+// Median of n (<= 8) timings: robust against the odd slow repetition.
+static float median_ms(float* v, int n) {
+  std::sort(v, v + n);
+  return n % 2 ? v[n / 2] : 0.5f * (v[n / 2 - 1] + v[n / 2]);
+}
+
 fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* stream, float* times_ms) {
   if (!p || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, "fsp_autotune: NULL argument");
   if (!p->ready) return fail(FSP_ERR_NOT_READY, "fsp_autotune: plan has no bound buffers or no precomputed transform");
@@ -715,7 +723,7 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
     for (int v = 0; v < fsp::NUM_VARIANTS && e == hipSuccess; ++v) {
       for (int i = 0; i < 5; ++i) p->var[i] = best[i];
       p->var[pass] = v;
-      float total = 0;
+      float rep_ms[8] = {};
       for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // r == 0 warms up
         fsp_status st = pass > 0 ? solve_one(p, rho, phi, s, 0, pass - 1) : FSP_OK;
         if (st == FSP_OK) e = hipEventRecord(e0, s);
@@ -731,9 +739,9 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (r > 0) total += ms;
+        if (r > 0) rep_ms[r - 1] = ms;
       }
-      const float ms = total / reps;
+      const float ms = median_ms(rep_ms, reps);
       if (times_ms) times_ms[pass * fsp::NUM_VARIANTS + v] = ms;
       if (e == hipSuccess && ms < best_ms) {
         best_ms = ms;
@@ -747,7 +755,7 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
     auto time_range = [&](const int* sched, float* out) -> hipError_t {
       for (int i = 0; i < 5; ++i) p->var[i] = sched[i];
       hipError_t r = hipSuccess;
-      float total = 0;
+      float rep_ms[8] = {};
       for (int k = 0; k <= reps && r == hipSuccess; ++k) {
         if ((st_range = solve_one(p, rho, phi, s, 0, 0)) != FSP_OK) return hipErrorInvalidValue;
         r = hipEventRecord(e0, s);
@@ -757,9 +765,9 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
         if (r == hipSuccess) r = hipEventSynchronize(e1);
         float ms = 0;
         if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
-        if (k > 0) total += ms;
+        if (k > 0) rep_ms[k - 1] = ms;
       }
-      *out = total / reps;
+      *out = median_ms(rep_ms, reps);
       return r;
     };
     int fused[5] = {best[0], fsp::FUSED, fsp::FUSED, fsp::FUSED, best[4]};

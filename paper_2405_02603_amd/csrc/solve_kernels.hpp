@@ -65,6 +65,14 @@ struct RowArgs {
 template <typename T>
 __device__ __forceinline__ cx<T> czero() { return {T(0), T(0)}; }
 
+// Load of a value that this launch reads exactly once (streamed, non-temporal).
+template <typename T>
+__device__ __forceinline__ cx<T> ld_once(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 w = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return {w.x, w.y};
+}
+
 // Store of a pass result.  Results that the next pass does not re-read soon
 // are streamed past the caches (non-temporal); the float32 axis-1 passes keep
 // normal stores, because their output is re-read by the next pass while it is
@@ -246,7 +254,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       const int b = q + NQ * j;
       const bool ok = on && cok && ((F::NB % NQ == 0) || b < F::NB);
 #pragma unroll
-      for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? base[(b + r * F::NB) * rs] : czero<T>();
+      for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? ld_once(&base[(b + r * F::NB) * rs]) : czero<T>();
     }
   };
   auto run_set = [&](cx<T>* base, const cx<T> (&raw)[F::J][F::R / 2], bool st) {
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv_pipe(ColArgs a) {
       const int b = q + NQ * j;
       const bool ok = on && ((F::NB % NQ == 0) || b < F::NB);
 #pragma unroll
-      for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? base[(b + r * F::NB) * rs] : czero<T>();
+      for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? ld_once(&base[(b + r * F::NB) * rs]) : czero<T>();
     }
   };
   auto run_set = [&](cx<T>* base, const T* g, bool on, const cx<T> (&raw)[F::J][F::R / 2]) {
@@ -673,7 +681,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
     const int b = q + NQ * j;
     const bool ok = rok && ((F::NB % NQ == 0) || b < F::NB);
 #pragma unroll
-    for (int r = 0; r < F::R; ++r) v[j][r] = (ok && r < F::R / 2) ? in[b + r * F::NB] : czero<T>();
+    for (int r = 0; r < F::R; ++r) v[j][r] = (ok && r < F::R / 2) ? ld_once(&in[b + r * F::NB]) : czero<T>();
     Dft<F::R, false, T>::run(v[j]);
   }
   if constexpr (K == 1) {
@@ -738,7 +746,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
 #pragma unroll
     for (int j = 0; j < JI; ++j) {
       const int k = q + NQ * j;
-      if (k <= LC) lds[idx(k)] = rok ? in[k] : czero<T>();
+      if (k <= LC) lds[idx(k)] = rok ? ld_once(&in[k]) : czero<T>();
     }
   }
   lds_barrier();
