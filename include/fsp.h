@@ -68,6 +68,10 @@ typedef enum { FSP_F32 = 0, FSP_F64 = 1 } fsp_prec;
 
 /* Plan flags. */
 #define FSP_FLAG_NONE 0u
+/* Also precompute the derivative tables of the Green's function (three more
+ * octants in the Green's buffer) and size the workspace for fsp_solve_grad
+ * (two spectra instead of one). */
+#define FSP_WANT_GRAD 1u
 
 typedef struct {
   int n[3];          /* grid points per axis; axis 2 is contiguous                     */
@@ -77,7 +81,7 @@ typedef struct {
   int prec;          /* fsp_prec: precision of rho, phi and the solve passes            */
   double alpha;      /* Vico-Greengard window factor, L = alpha |hi - lo|; 0 -> 1.1     */
   double g0;         /* Hockney-Eastwood K[0]; NaN -> 1/(4 pi)                           */
-  unsigned flags;    /* FSP_FLAG_*                                                      */
+  unsigned flags;    /* FSP_FLAG_NONE or FSP_WANT_GRAD; other bits: FSP_ERR_INVALID_ARG */
 } fsp_plan_desc;
 
 /* Validate a descriptor and build a plan.  Host only: no device memory is
@@ -130,6 +134,24 @@ fsp_status fsp_solve(fsp_plan p, const void* rho, void* phi, void* stream);
  * only by pass 0 and phi written only by pass 4 (the other pointer may be
  * NULL when its pass is outside the range). */
 fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, int last, void* stream);
+
+/* The gradient of the solution: grad[a] = d phi / d x_a (E = -grad), as
+ * three device arrays [3][n0][n1][n2] in the plan's precision, and phi too
+ * when phi is not NULL (phi may equal rho; grad must not overlap phi).
+ * The paper names the field E = -grad(phi) for its particle application
+ * (Appendix B) without a method; here each component is the same discrete
+ * convolution as the potential with the derivative of the kernel, which is
+ * odd along its axis: for Hockney-Eastwood -x_a / (4 pi |x|^3) (0 at the
+ * origin), for Vico-Greengard the inverse transform of i k_a times eq. (3) on
+ * the 4N grid.  Its transform on the doubled grid is -i times a real octant
+ * (sine transform along a), stored by fsp_precompute.  The forward transforms
+ * along axes 2 and 1 run once; then for each component the axis-0 pass reads
+ * that spectrum and writes the second half of the workspace, and the inverse
+ * passes produce the component.  Needs a plan created with FSP_WANT_GRAD
+ * (else FSP_ERR_INVALID_ARG); FSP_ERR_NOT_READY before bind + precompute.
+ * Uses the plan's schedule with separate passes 1-3.  Asynchronous on
+ * `stream`; allocates nothing. */
+fsp_status fsp_solve_grad(fsp_plan p, const void* rho, void* phi, void* grad, void* stream);
 
 /* Schedules.  Every pass has NUM_VARIANTS = 3 kernel variants (radix plan,
  * threads per pencil, tile); variants[i] selects the one for pass i (0..4,
@@ -188,6 +210,12 @@ fsp_status fsp_plan_destroy(fsp_plan p);
  * * tile + k2 % tile), T = ceil((n2 + 1) / tile); slots with k2 > n2 hold 0.
  * Either pointer may be NULL. */
 fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* tile);
+
+/* Byte offset in the Green's buffer of octant `component`: 0 the potential's
+ * (as fsp_plan_ghat_layout), 1 + a the derivative table along axis a (plans
+ * with FSP_WANT_GRAD only, else FSP_ERR_INVALID_ARG).  Same blocked layout and
+ * tile; a derivative octant holds T with transform -i T, T odd along a. */
+fsp_status fsp_plan_octant_offset(fsp_plan p, int component, size_t* offset);
 
 /* Model bytes that one solve moves through HBM with this plan's schedule
  * (reads + writes of the five passes, the Green's octant included). */

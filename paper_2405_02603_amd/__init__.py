@@ -67,11 +67,12 @@ class Plan:
     "vico_dct" (Section 2.4, (2N+1)^3 DCT-I precompute).
     ``prec``: "f32" or "f64" (precision of rho, phi and the solve passes; the
     precompute always runs in float64).
+    ``grad``: also build the derivative tables for ``solve_grad``.
     """
 
     def __init__(self, n, lo=(-0.5, -0.5, -0.5), hi=(0.5, 0.5, 0.5), greens: str = "vico_dct",
                  prec: str = "f32", alpha: float = 1.1, g0: Optional[float] = None, device=None,
-                 precompute: bool = True, stream=None, bind: bool = True):
+                 precompute: bool = True, stream=None, bind: bool = True, grad: bool = False):
         torch = _torch()
         self._lib = _lib.load()
         if greens not in GREENS:
@@ -97,7 +98,8 @@ class Plan:
         desc.prec = PREC[prec]
         desc.alpha = self.alpha
         desc.g0 = float("nan") if g0 is None else float(g0)
-        desc.flags = 0
+        self.grad = bool(grad)
+        desc.flags = _lib.FSP_WANT_GRAD if self.grad else 0
         h = ctypes.c_void_p()
         check(self._lib.fsp_plan_create(ctypes.byref(desc), ctypes.byref(h)), "fsp_plan_create")
         self._h = h
@@ -143,18 +145,22 @@ class Plan:
         check(self._lib.fsp_plan_share_ghat(self._h, src._h), "fsp_plan_share_ghat")
         self._shared_from = src  # keep src (and its buffer) alive
 
-    def ghat_octant(self):
-        """The stored transform octant as a [n0+1][n1+1][n2+1] tensor (scaled by V/(8 n0 n1 n2))."""
+    def ghat_octant(self, component: int = 0):
+        """A stored octant as a [n0+1][n1+1][n2+1] tensor (scaled by V/(8 n0 n1 n2)): component 0
+        the transform of the Green's function, 1 + a the real T of a derivative table (transform -i T)."""
         torch = _torch()
-        src = self._shared_from.ghat_octant() if self._shared_from is not None else None
+        src = self._shared_from.ghat_octant(component) if self._shared_from is not None else None
         if src is not None:
             return src
+        off = ctypes.c_size_t()
+        check(self._lib.fsp_plan_octant_offset(self._h, int(component), ctypes.byref(off)), "fsp_plan_octant_offset")
+        off = int(off.value)
         n0, n1, n2 = self.n
         esz = 8 if self.prec == "f64" else 4
         t = self.octant_tile
         tiles = (n2 + 1 + t - 1) // t
         nb = (n1 + 1) * tiles * (n0 + 1) * t * esz
-        raw = self.ghat_buf[self.octant_offset:self.octant_offset + nb].view(self.dtype)
+        raw = self.ghat_buf[off:off + nb].view(self.dtype)
         blocked = raw.view(n1 + 1, tiles, n0 + 1, t)            # [k1][tile][k0][c]
         full = blocked.permute(2, 0, 1, 3).reshape(n0 + 1, n1 + 1, tiles * t)
         return full[:, :, : n2 + 1]
@@ -181,6 +187,29 @@ class Plan:
             check(self._lib.fsp_solve(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                       _stream_ptr(stream)), "fsp_solve")
         return out
+
+    def solve_grad(self, rho, grad=None, phi=None, want_phi: bool = False, stream=None):
+        """grad = (d phi/dx0, d phi/dx1, d phi/dx2) as a [3][n0][n1][n2] tensor, and phi when
+        ``phi`` is given or ``want_phi``; returns (grad, phi or None).  See fsp_solve_grad."""
+        torch = _torch()
+        if not self.grad:
+            raise ValueError("create the plan with grad=True")
+        self._check_field(rho, "rho")
+        if grad is None:
+            grad = torch.empty((3,) + self.n, dtype=self.dtype, device=self.device)
+        if tuple(grad.shape) != (3,) + self.n or grad.dtype != self.dtype or not grad.is_contiguous() \
+                or grad.device != self.device:
+            raise ValueError(f"grad must be a contiguous {self.dtype} tensor of shape {(3,) + self.n}")
+        if phi is None and want_phi:
+            phi = torch.empty_like(rho)
+        if phi is not None:
+            self._check_field(phi, "phi")
+        with torch.cuda.device(self.device):
+            check(self._lib.fsp_solve_grad(self._h, ctypes.c_void_p(rho.data_ptr()),
+                                           ctypes.c_void_p(phi.data_ptr() if phi is not None else 0),
+                                           ctypes.c_void_p(grad.data_ptr()), _stream_ptr(stream)),
+                  "fsp_solve_grad")
+        return grad, phi
 
     def solve_passes(self, rho, out, first: int, last: int, stream=None):
         """Run passes first..last (0..4) of a solve; see fsp_solve_passes."""

@@ -23,6 +23,7 @@ FSP_ERR_DEVICE = 6
 GREENS = {"hockney": 0, "vico": 1, "vico_dct": 2}
 NUM_VARIANTS = 3
 FUSED = 3  # schedule value of passes 1-3 selecting the fused small-grid kernel
+FSP_WANT_GRAD = 1  # plan flag: derivative tables and a workspace for fsp_solve_grad
 PREC = {"f32": 0, "f64": 1}
 
 # every symbol include/fsp.h declares
@@ -32,6 +33,7 @@ EXPORTS = (
     "fsp_plan_ghat_layout", "fsp_plan_model_bytes", "fsp_status_str", "fsp_last_error", "fsp_version",
     "fsp_batch_create", "fsp_batch_launch", "fsp_batch_destroy",
     "fsp_plan_get_schedule", "fsp_plan_set_schedule", "fsp_autotune",
+    "fsp_solve_grad", "fsp_plan_octant_offset",
 )
 
 
@@ -91,6 +93,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "fsp_batch_destroy": (c_int, [P]),
         "fsp_plan_ghat_layout": (c_int, [P, POINTER(c_size_t), POINTER(c_int)]),
         "fsp_plan_model_bytes": (c_int, [P, POINTER(c_double)]),
+        "fsp_solve_grad": (c_int, [P, P, P, P, P]),
+        "fsp_plan_octant_offset": (c_int, [P, c_int, POINTER(c_size_t)]),
         "fsp_status_str": (c_char_p, [c_int]),
         "fsp_last_error": (c_char_p, []),
         "fsp_version": (c_char_p, []),

@@ -23,6 +23,7 @@ namespace fsp {
 hipError_t solve_f32(const SolveGeom& g, int first, int last, hipStream_t s);
 hipError_t solve_f64(const SolveGeom& g, int first, int last, hipStream_t s);
 hipError_t greens_he_kernel(double* K, const int n[3], const double h[3], double g0, hipStream_t s);
+hipError_t greens_he_grad_kernel(double* D, const int n[3], const double h[3], int axis, hipStream_t s);
 hipError_t greens_vico_spectrum(double* G, const int samples[3], const double f[3], double L, bool fft_order,
                                 hipStream_t s);
 hipError_t greens_contract(const double* X, double* Y, const double* C, int nout, int nin, long long rest,
@@ -137,6 +138,46 @@ void dft_cos_matrix(std::vector<double>& C, int nout, int s) {
     }
 }
 
+// Rows m < nout of the sine sum that turns the (period+1) non-negative
+// frequency samples l of an even spectrum into the derivative of its inverse
+// transform along that axis: C[m][l] = 2 (-kfac l) sin(pi l m / period)
+// (the end samples carry sin = 0).
+void sine_k_matrix(std::vector<double>& C, int nout, int period, double kfac) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  const int nin = period + 1;
+  C.assign((size_t)nout * nin, 0.0);
+  for (int m = 0; m < nout; ++m)
+    for (int l = 1; l < period; ++l) {
+      const long long t = ((long long)l * m) % (2LL * period);
+      C[(size_t)m * nin + l] = (double)(-2.0L * kfac * l * sinl(pi * (long double)t / (long double)period));
+    }
+}
+
+// The same on the full grid of s samples in FFT order (signed frequency
+// l' = l or l - s): C[m][l] = -(kfac l') sin(2 pi l m / s).
+void dft_sin_k_matrix(std::vector<double>& C, int nout, int s, double kfac) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  C.resize((size_t)nout * s);
+  for (int m = 0; m < nout; ++m)
+    for (int l = 0; l < s; ++l) {
+      const long long t = ((long long)l * m) % s;
+      const long long ls = l < s / 2 ? l : l - s;
+      C[(size_t)m * s + l] = (double)(-(long double)kfac * ls * sinl(2.0L * pi * (long double)t / (long double)s));
+    }
+}
+
+// Sine transform of an odd table on [0, n] (0 at both ends), the transform of
+// its odd extension to 2n points up to a factor -i: C[k][m] = 2 sin(pi k m / n).
+void dst1_matrix(std::vector<double>& C, int n) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  C.assign((size_t)(n + 1) * (n + 1), 0.0);
+  for (int k = 0; k <= n; ++k)
+    for (int m = 1; m < n; ++m) {
+      const long long t = ((long long)k * m) % (2LL * n);
+      C[(size_t)k * (n + 1) + m] = (double)(2.0L * sinl(pi * (long double)t / (long double)n));
+    }
+}
+
 struct DeviceGuard {
   int prev = -1;
   bool changed = false;
@@ -169,6 +210,9 @@ struct fsp_plan_s {
   int chunks = 1;       // column chunks for passes 1-3
   int gather_min = fsp::CONV_GATHER_MIN_BLOCKS;  // axis-0 grid size from which the lone column is gathered
   size_t tw_row_off[fsp::NUM_PLANS]{}, tw_c1_off[fsp::NUM_PLANS]{}, tw_c0_off[fsp::NUM_PLANS]{}, oct_off = 0;
+  bool grad = false;        // FSP_WANT_GRAD: derivative octants and a second workspace
+  size_t grad_off[3]{};     // offsets of the derivative octants in the Green's buffer
+  size_t work1_bytes = 0;   // one workspace S (the second, if any, follows it)
   int var[5]{};  // schedule variant of each pass
   size_t ghat_bytes = 0, work_bytes = 0, pre_bytes = 0;
   std::vector<char> tw_host;      // image of [0, oct_off) of the Green's buffer
@@ -272,6 +316,7 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     if (d.greens == FSP_VICO && d.n[a] > 256)
       return fail(FSP_ERR_UNSUPPORTED_SIZE, "fsp_plan_create: the (4N)^3 Vico-Greengard route is limited to n <= 256");
   }
+  if (d.flags & ~(unsigned)FSP_WANT_GRAD) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: unknown flags");
   const double alpha = d.alpha == 0.0 ? 1.1 : d.alpha;
   if (!std::isfinite(alpha) || !(alpha > 1.0))
     return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: alpha must exceed 1 (0 selects 1.1)");
@@ -305,8 +350,10 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
   p->gtile = d.prec == FSP_F64 ? fsp::conv_tile_f64(2 * p->n[0]) : fsp::conv_tile_f32(2 * p->n[0]);
   {
     const size_t tiles = (p->n[2] + 1 + p->gtile - 1) / p->gtile;
-    p->ghat_bytes =
-        align_up(p->oct_off + (size_t)(p->n[1] + 1) * tiles * (p->n[0] + 1) * p->gtile * p->rb, 256);
+    const size_t oct = align_up((size_t)(p->n[1] + 1) * tiles * (p->n[0] + 1) * p->gtile * p->rb, 256);
+    p->grad = (d.flags & FSP_WANT_GRAD) != 0;
+    for (int a = 0; a < 3; ++a) p->grad_off[a] = p->grad ? p->oct_off + (a + 1) * oct : 0;
+    p->ghat_bytes = p->oct_off + (p->grad ? 4 : 1) * oct;
   }
   {
     long long pad = 0;
@@ -315,7 +362,8 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     if (const char* e = std::getenv("FSP_CHUNKS")) p->chunks = std::max(1, std::atoi(e));
     if (const char* e = std::getenv("FSP_CONV_GATHER_MIN")) p->gather_min = std::max(0, std::atoi(e));
   }
-  p->work_bytes = align_up((size_t)p->n[0] * p->plane * cb, 256);
+  p->work1_bytes = align_up((size_t)p->n[0] * p->plane * cb, 256);
+  p->work_bytes = (p->grad ? 2 : 1) * p->work1_bytes;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(TuneKey{p->n[0], p->n[1], p->n[2], d.prec});
@@ -344,7 +392,7 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     cm = (n0 + 1) * 4 * n0 + (n1 + 1) * 4 * n1 + (n2 + 1) * 4 * n2 + (n0 + 1) * (n0 + 1) + (n1 + 1) * (n1 + 1) +
          (n2 + 1) * (n2 + 1);
   }
-  p->pre_bytes = align_up(a * 8, 256) + align_up(b * 8, 256) + align_up(cm * 8, 256);
+  p->pre_bytes = align_up(a * 8, 256) + align_up(b * 8, 256) + align_up(cm * 8 * (p->grad ? 4 : 1), 256);
   *out = p;
   g_err.clear();
   return FSP_OK;
@@ -373,6 +421,14 @@ fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* tile) {
   if (!p) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_ghat_layout: NULL plan");
   if (octant_offset) *octant_offset = p->oct_off;
   if (tile) *tile = p->gtile;
+  return FSP_OK;
+}
+
+fsp_status fsp_plan_octant_offset(fsp_plan p, int component, size_t* offset) {
+  if (!p || !offset) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_octant_offset: NULL argument");
+  if (component < 0 || component > 3 || (component > 0 && !p->grad))
+    return fail(FSP_ERR_INVALID_ARG, "fsp_plan_octant_offset: component must be 0, or 1-3 on a plan with FSP_WANT_GRAD");
+  *offset = component == 0 ? p->oct_off : p->grad_off[component - 1];
   return FSP_OK;
 }
 
@@ -428,12 +484,53 @@ fsp_status fsp_plan_share_ghat(fsp_plan dst, fsp_plan src) {
   bool same = a.greens == b.greens && a.prec == b.prec && dst->alpha == src->alpha && dst->g0 == src->g0;
   for (int i = 0; i < 3; ++i) same = same && a.n[i] == b.n[i] && a.lo[i] == b.lo[i] && a.hi[i] == b.hi[i];
   if (!same) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_share_ghat: plans differ in kernel, grid, box or precision");
+  if (dst->grad && !src->grad)
+    return fail(FSP_ERR_INVALID_ARG, "fsp_plan_share_ghat: the destination needs derivative tables the source lacks");
   if (!src->ready) return fail(FSP_ERR_NOT_READY, "fsp_plan_share_ghat: source plan has no precomputed transform");
   if (!dst->bound) return fail(FSP_ERR_NOT_READY, "fsp_plan_share_ghat: bind the destination plan first");
   if (src->device != dst->device) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_share_ghat: plans on different devices");
   dst->ghat_read = src->ghat_read;
   dst->ready = true;
   return FSP_OK;
+}
+
+// Matrices of one component's precompute, in the order they are used: for
+// Vico-Greengard the three spectrum -> kernel contractions, then the three
+// kernel -> transform contractions.  Component 0 is the potential; component
+// 1 + a the derivative along axis a, whose axis-a matrices are the sine forms.
+static void component_matrices(const fsp_plan_s* p, int comp, std::vector<double>& cm, std::vector<size_t>& moff) {
+  const int* n = p->n;
+  const int gk = p->d.greens;
+  const int ax = comp - 1;
+  std::vector<double> tmp;
+  auto add = [&](const std::vector<double>& m) {
+    moff.push_back(cm.size());
+    cm.insert(cm.end(), m.begin(), m.end());
+  };
+  if (gk == FSP_VICO_DCT) {
+    for (int a = 0; a < 3; ++a) {
+      if (a == ax)
+        sine_k_matrix(tmp, n[a] + 1, 2 * n[a], M_PI / (2.0 * n[a] * p->h[a]));
+      else
+        dct1_matrix(tmp, n[a] + 1, 2 * n[a]);
+      add(tmp);
+    }
+  } else if (gk == FSP_VICO) {
+    for (int a = 0; a < 3; ++a) {
+      if (a == ax)
+        dft_sin_k_matrix(tmp, n[a] + 1, 4 * n[a], 2.0 * M_PI / (4.0 * n[a] * p->h[a]));
+      else
+        dft_cos_matrix(tmp, n[a] + 1, 4 * n[a]);
+      add(tmp);
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (a == ax)
+      dst1_matrix(tmp, n[a]);
+    else
+      dct1_matrix(tmp, n[a] + 1, n[a]);
+    add(tmp);
+  }
 }
 
 fsp_status fsp_precompute(fsp_plan p, void* stream) {
@@ -445,30 +542,13 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int* n = p->n;
   const int gk = p->d.greens;
-  // cosine matrices, in the order they are used
+  const int ncomp = p->grad ? 4 : 1;
+  // all components' matrices, uploaded once (the host image outlives the copy)
   std::vector<double>& cm = p->cmat_host;
   cm.clear();
   std::vector<size_t> moff;
-  std::vector<double> tmp;
-  auto add = [&](const std::vector<double>& m) {
-    moff.push_back(cm.size());
-    cm.insert(cm.end(), m.begin(), m.end());
-  };
-  if (gk == FSP_VICO_DCT) {
-    for (int a = 0; a < 3; ++a) {
-      dct1_matrix(tmp, n[a] + 1, 2 * n[a]);
-      add(tmp);
-    }
-  } else if (gk == FSP_VICO) {
-    for (int a = 0; a < 3; ++a) {
-      dft_cos_matrix(tmp, n[a] + 1, 4 * n[a]);
-      add(tmp);
-    }
-  }
-  for (int a = 0; a < 3; ++a) {
-    dct1_matrix(tmp, n[a] + 1, n[a]);
-    add(tmp);
-  }
+  for (int c = 0; c < ncomp; ++c) component_matrices(p, c, cm, moff);
+  const size_t per_comp = moff.size() / ncomp;
   const size_t n0 = n[0], n1 = n[1], n2 = n[2];
   size_t a_elems, b_elems;
   if (gk == FSP_HOCKNEY) {
@@ -492,46 +572,51 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
   }
   p->ready = false;
   e = hipMemcpyAsync(C, cm.data(), cm.size() * 8, hipMemcpyHostToDevice, s);
-  int mi = 0;
-  // current layout dims, leading axis first
-  long long dims[3];
-  double scale = p->V / (8.0 * n0 * n1 * n2);  // folds V and the 1/M^3 of the inverse transform
-  double* X = A;
-  double* Y = B;
-  auto contract = [&](int nout) {
-    // leading axis dims[0] -> nout, rotate to the back
-    const long long rest = dims[1] * dims[2];
-    if (e == hipSuccess)
-      e = fsp::greens_contract(X, Y, C + moff[mi], nout, (int)dims[0], rest, s);
-    ++mi;
-    const long long d0 = dims[0];
-    (void)d0;
-    dims[0] = dims[1];
-    dims[1] = dims[2];
-    dims[2] = nout;
-    std::swap(X, Y);
-  };
-  if (gk == FSP_HOCKNEY) {
-    if (e == hipSuccess) e = fsp::greens_he_kernel(X, n, p->h, p->g0, s);
-    dims[0] = n0 + 1; dims[1] = n1 + 1; dims[2] = n2 + 1;
-  } else {
-    const bool full = gk == FSP_VICO;
-    int samples[3];
-    double f[3];
-    for (int a = 0; a < 3; ++a) {
-      samples[a] = full ? 4 * n[a] : 2 * n[a] + 1;
-      f[a] = M_PI / (2.0 * n[a] * p->h[a]);  // k = 2 pi l / (4 n h)
+  for (int comp = 0; comp < ncomp && e == hipSuccess; ++comp) {
+    size_t mi = comp * per_comp;
+    long long dims[3];  // current layout dims, leading axis first
+    double scale = p->V / (8.0 * n0 * n1 * n2);  // folds V and the 1/M^3 of the inverse transform
+    double* X = A;
+    double* Y = B;
+    auto contract = [&](int nout) {
+      // leading axis dims[0] -> nout, rotated to the back
+      const long long rest = dims[1] * dims[2];
+      if (e == hipSuccess) e = fsp::greens_contract(X, Y, C + moff[mi], nout, (int)dims[0], rest, s);
+      ++mi;
+      dims[0] = dims[1];
+      dims[1] = dims[2];
+      dims[2] = nout;
+      std::swap(X, Y);
+    };
+    if (gk == FSP_HOCKNEY) {
+      if (comp == 0)
+        e = fsp::greens_he_kernel(X, n, p->h, p->g0, s);
+      else
+        e = fsp::greens_he_grad_kernel(X, n, p->h, comp - 1, s);
+      dims[0] = n0 + 1;
+      dims[1] = n1 + 1;
+      dims[2] = n2 + 1;
+    } else {
+      const bool full = gk == FSP_VICO;
+      int samples[3];
+      double f[3];
+      for (int a = 0; a < 3; ++a) {
+        samples[a] = full ? 4 * n[a] : 2 * n[a] + 1;
+        f[a] = M_PI / (2.0 * n[a] * p->h[a]);  // k = 2 pi l / (4 n h)
+      }
+      e = fsp::greens_vico_spectrum(X, samples, f, p->L, full, s);
+      dims[0] = samples[0];
+      dims[1] = samples[1];
+      dims[2] = samples[2];
+      for (int a = 0; a < 3; ++a) contract(n[a] + 1);
+      // inverse transform on the 4n grid: 1 / prod(4 n_d h_d) = 1 / (64 n0 n1 n2 V)
+      scale /= 64.0 * n0 * n1 * n2 * p->V;
     }
-    if (e == hipSuccess) e = fsp::greens_vico_spectrum(X, samples, f, p->L, full, s);
-    dims[0] = samples[0]; dims[1] = samples[1]; dims[2] = samples[2];
     for (int a = 0; a < 3; ++a) contract(n[a] + 1);
-    // inverse transform on the 4n grid: 1 / prod(4 n_d h_d) = 1 / (64 n0 n1 n2 V)
-    scale /= 64.0 * n0 * n1 * n2 * p->V;
+    const size_t off = comp == 0 ? p->oct_off : p->grad_off[comp - 1];
+    if (e == hipSuccess)
+      e = fsp::greens_store_octant(X, static_cast<char*>(p->ghat) + off, p->d.prec == FSP_F64, n, p->gtile, scale, s);
   }
-  for (int a = 0; a < 3; ++a) contract(n[a] + 1);
-  if (e == hipSuccess)
-    e = fsp::greens_store_octant(X, static_cast<char*>(p->ghat) + p->oct_off, p->d.prec == FSP_F64, n, p->gtile,
-                                 scale, s);
   if (e == hipSuccess) e = hipMemcpyAsync(p->ghat, p->tw_host.data(), p->tw_host.size(), hipMemcpyHostToDevice, s);
   (void)hipFreeAsync(A, s);
   (void)hipFreeAsync(B, s);
@@ -543,7 +628,11 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
 }
 
 // Shape fields shared by every item of a launch group (items filled by the caller).
-static fsp::SolveGeom group_geom(const fsp_plan_s* p) {
+static fsp::SolveGeom group_geom(const fsp_plan_s* p, const int* var);
+static fsp::SolveGeom group_geom(const fsp_plan_s* p) { return group_geom(p, p->var); }
+
+// Shape fields with an explicit schedule.
+static fsp::SolveGeom group_geom(const fsp_plan_s* p, const int* var) {
   fsp::SolveGeom g{};
   g.items = 0;
   g.n0 = p->n[0];
@@ -554,14 +643,14 @@ static fsp::SolveGeom group_geom(const fsp_plan_s* p) {
   g.chunks = p->chunks;
   g.gather_min = p->gather_min;
   const char* gb = static_cast<const char*>(p->ghat_read);
-  for (int i = 0; i < 5; ++i) g.var[i] = p->var[i];
-  const int pr1 = fsp::row_cfg<float>(p->n[2], p->var[0]).pid, pr5 = fsp::row_cfg<float>(p->n[2], p->var[4]).pid;
-  const bool fused = p->var[1] == fsp::FUSED;
-  const int pc2 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], p->var[1]).pid;
-  const int pc4 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], p->var[3]).pid;
+  for (int i = 0; i < 5; ++i) g.var[i] = var[i];
+  const int pr1 = fsp::row_cfg<float>(p->n[2], var[0]).pid, pr5 = fsp::row_cfg<float>(p->n[2], var[4]).pid;
+  const bool fused = var[1] == fsp::FUSED;
+  const int pc2 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], var[1]).pid;
+  const int pc4 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], var[3]).pid;
   const int pc3 = fused                     ? 0
-                  : p->d.prec == FSP_F64 ? fsp::conv_cfg<double>(2 * p->n[0], p->var[2]).pid
-                                              : fsp::conv_cfg<float>(2 * p->n[0], p->var[2]).pid;
+                  : p->d.prec == FSP_F64 ? fsp::conv_cfg<double>(2 * p->n[0], var[2]).pid
+                                              : fsp::conv_cfg<float>(2 * p->n[0], var[2]).pid;
   for (int i = 0; i < 5; ++i) g.tw_row[i] = g.tw_c1[i] = nullptr;
   g.tw_row[0] = gb + p->tw_row_off[pr1];
   g.tw_row[4] = gb + p->tw_row_off[pr5];
@@ -665,6 +754,50 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
   hipError_t e = guard.enter(p->device);
   if (e != hipSuccess) return fail_hip(e, "fsp_solve_passes: hipSetDevice");
   return solve_one(p, rho, phi, reinterpret_cast<hipStream_t>(stream), first, last);
+}
+
+fsp_status fsp_solve_grad(fsp_plan p, const void* rho, void* phi, void* grad, void* stream) {
+  if (!p || !rho || !grad) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_grad: NULL argument");
+  if (!p->grad) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_grad: the plan was created without FSP_WANT_GRAD");
+  if (!p->ready) return fail(FSP_ERR_NOT_READY, "fsp_solve_grad: plan has no bound buffers or no precomputed transform");
+  const size_t field = (size_t)p->n[0] * p->n[1] * p->n[2] * p->rb;
+  if (phi) {
+    const char *g0 = static_cast<const char*>(grad), *f = static_cast<const char*>(phi);
+    if (f < g0 + 3 * field && g0 < f + field)
+      return fail(FSP_ERR_INVALID_ARG, "fsp_solve_grad: phi overlaps grad");
+  }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(p->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_solve_grad: hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool f64 = p->d.prec == FSP_F64;
+  // separate passes 1-3, and an axis-0 kernel that can write out of place
+  int var[5];
+  for (int i = 0; i < 5; ++i) var[i] = p->var[i];
+  if (var[1] == fsp::FUSED) var[1] = var[2] = var[3] = 0;
+  if (f64 ? fsp::conv_pipelined<double>(2 * p->n[0], var[2]) : fsp::conv_pipelined<float>(2 * p->n[0], var[2]))
+    var[2] = 0;
+  fsp::SolveGeom g = group_geom(p, var);
+  add_item(g, p, rho, nullptr);
+  e = run_group(g, f64, 0, 1, s);  // the forward transforms along axes 2 and 1, once
+  const char* gb = static_cast<const char*>(p->ghat_read);
+  void* work2 = static_cast<char*>(p->work) + p->work1_bytes;
+  for (int a = 0; a < 3 && e == hipSuccess; ++a) {  // P3 reads S, writes the second workspace
+    g.comp = 1 + a;
+    g.ghat[0] = gb + p->grad_off[a];
+    g.work_out[0] = work2;
+    g.phi[0] = static_cast<char*>(grad) + a * field;
+    e = run_group(g, f64, 2, 4, s);
+  }
+  if (phi && e == hipSuccess) {  // the potential last: its axis-0 pass works in place on S
+    g.comp = 0;
+    g.ghat[0] = gb + p->oct_off;
+    g.work_out[0] = nullptr;
+    g.phi[0] = phi;
+    e = run_group(g, f64, 2, 4, s);
+  }
+  if (e != hipSuccess) return fail_hip(e, "fsp_solve_grad");
+  return FSP_OK;
 }
 
 fsp_status fsp_plan_get_schedule(fsp_plan p, int* variants) {

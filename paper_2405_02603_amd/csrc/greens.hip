@@ -16,6 +16,11 @@
 //     the octant outputs m_d <= n_d only (a real cosine sum, since the grid
 //     data are real and even), then as Hockney-Eastwood.
 //
+// Derivative tables (the kernel's derivative along axis a, odd along a): the
+// same steps with sine forms along a -- -k_a-weighted sine sums from the
+// spectrum, and a sine transform of the odd extension on the doubled grid,
+// whose transform is -i times the stored real octant.
+//
 // Each one-axis transform is a dense contraction of the leading axis with a
 // small cosine matrix that also rotates the axes, Y[rest][m] = sum_l C[m][l]
 // X[l][rest]: after three of them the data are back in [m0][m1][m2] order.
@@ -35,6 +40,23 @@ __global__ __launch_bounds__(256) void k_he_kernel(double* K, int n0, int n1, in
   const double x = m0 * h0, y = m1 * h1, z = m2 * h2;
   const double r = sqrt(x * x + y * y + z * z);
   K[i] = (i == 0) ? g0 : 1.0 / (4.0 * M_PI * r);
+}
+
+// Derivative of the Hockney-Eastwood kernel along `axis` on the octant:
+// D[m] = -x_a / (4 pi |x|^3), x = m h, with 0 (an odd function's value) at m = 0.
+__global__ __launch_bounds__(256) void k_he_grad_kernel(double* D, int n0, int n1, int n2, double h0, double h1,
+                                                        double h2, int axis) {
+  const long long total = (long long)(n0 + 1) * (n1 + 1) * (n2 + 1);
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int m2 = (int)(i % (n2 + 1));
+  const long long t = i / (n2 + 1);
+  const int m1 = (int)(t % (n1 + 1));
+  const int m0 = (int)(t / (n1 + 1));
+  const double x = m0 * h0, y = m1 * h1, z = m2 * h2;
+  const double r2 = x * x + y * y + z * z;
+  const double xa = axis == 0 ? x : (axis == 1 ? y : z);
+  D[i] = (i == 0) ? 0.0 : -xa / (4.0 * M_PI * r2 * sqrt(r2));
 }
 
 // Samples of eq. (3): 2 sin^2(L|k|/2) / |k|^2, with L^2/2 at k = 0.
@@ -145,6 +167,13 @@ static unsigned grid1(long long n) { return (unsigned)((n + 255) / 256); }
 hipError_t greens_he_kernel(double* K, const int n[3], const double h[3], double g0, hipStream_t s) {
   const long long total = (long long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
   hipLaunchKernelGGL(k_he_kernel, dim3(grid1(total)), dim3(256), 0, s, K, n[0], n[1], n[2], h[0], h[1], h[2], g0);
+  return hipGetLastError();
+}
+
+hipError_t greens_he_grad_kernel(double* D, const int n[3], const double h[3], int axis, hipStream_t s) {
+  const long long total = (long long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
+  hipLaunchKernelGGL(k_he_grad_kernel, dim3(grid1(total)), dim3(256), 0, s, D, n[0], n[1], n[2], h[0], h[1], h[2],
+                     axis);
   return hipGetLastError();
 }
 

@@ -50,6 +50,8 @@ struct ColArgs {
   long long g_k1_stride;      // P3: reals between Green's blocks k1 (tiles (n0+1) TC)
   int ntail;                  // P3: leading blocks that gather column ncols - 1 over TC k1 pairs
   int gather_min;             // P3 (host side): grid size from which the launcher gathers
+  int comp;                   // P3: 0 potential (real multiply); 1 + a derivative along axis a
+  void* out[MAX_ITEMS];       // P3: result spectrum of each item (NULL: in place in data)
 };
 
 struct RowArgs {
@@ -74,14 +76,15 @@ __device__ __forceinline__ cx<T> ld_once(const cx<T>* p) {
 }
 
 // Store of a pass result.  Results that the next pass does not re-read soon
-// are streamed past the caches (non-temporal); the float32 axis-1 passes keep
-// normal stores, because their output is re-read by the next pass while it is
-// still in the memory-side cache.
+// are streamed past the caches (non-temporal); in float32 the axis-2 forward
+// pass and the axis-1 passes keep normal stores, because their output is
+// re-read by the next pass while part of it is still in the memory-side cache
+// (measured: streaming those is slower, streaming the others is faster).
 enum PassKind { PASS_ROW_FWD, PASS_COL_FWD, PASS_CONV, PASS_COL_INV, PASS_ROW_INV };
 
 template <typename T, int KIND>
 __device__ __forceinline__ void put(cx<T>* p, cx<T> v) {
-  constexpr bool streamed = sizeof(T) == 8 || (KIND != PASS_COL_FWD && KIND != PASS_COL_INV);
+  constexpr bool streamed = sizeof(T) == 8 || KIND == PASS_CONV || KIND == PASS_ROW_INV;
   if constexpr (streamed) {
     typedef T v2 __attribute__((ext_vector_type(2)));
     v2 w;
@@ -248,6 +251,22 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   const bool two = cok && !(p == 0 || p == a.n1);
   cx<T>* base_a = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)p * a.outer_stride + col;
   cx<T>* base_b = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)(2 * a.n1 - p) * a.outer_stride + col;
+  cx<T>* obase = reinterpret_cast<cx<T>*>(a.out[blockIdx.y] ? a.out[blockIdx.y] : a.data[blockIdx.y]);
+  cx<T>* out_a = obase + (long long)p * a.outer_stride + col;
+  cx<T>* out_b = obase + (long long)(2 * a.n1 - p) * a.outer_stride + col;
+  // The derivative tables are odd along their axis: their transform is -i T with
+  // the real octant T read at the folded frequency and negated on the upper half
+  // of that axis (k0 > n0; for axis 1 the partner 2 n1 - p; axis 2 holds k2 <= n2).
+  const int comp = a.comp;
+  auto multiply = [&](cx<T>& w, T g, int k0, bool upper_k1) {
+    if (comp == 0) {
+      w = cscale(w, g);
+    } else {
+      const bool neg = comp == 1 ? (k0 > L / 2) : (comp == 2 && upper_k1);
+      const T t = neg ? -g : g;
+      w = cx<T>{t * w.y, -t * w.x};  // w * (-i t)
+    }
+  };
   auto load_set = [&](const cx<T>* base, bool on, cx<T> (&raw)[F::J][F::R / 2]) {
 #pragma unroll
     for (int j = 0; j < F::J; ++j) {
@@ -257,7 +276,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? ld_once(&base[(b + r * F::NB) * rs]) : czero<T>();
     }
   };
-  auto run_set = [&](cx<T>* base, const cx<T> (&raw)[F::J][F::R / 2], bool st) {
+  auto run_set = [&](cx<T>* base, const cx<T> (&raw)[F::J][F::R / 2], bool st, bool upper_k1) {
     cx<T> v[F::J][F::R];
 #pragma unroll
     for (int j = 0; j < F::J; ++j) {
@@ -271,7 +290,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
         const int b = q + NQ * j;
         if (st && ((F::NB % NQ == 0) || b < F::NB)) {
 #pragma unroll
-          for (int m = 0; m < F::R; ++m) v[j][m] = cscale(v[j][m], gv[j][m]);
+          for (int m = 0; m < F::R; ++m) multiply(v[j][m], gv[j][m], b + m * F::NB, upper_k1);
           Dft<F::R, true, T>::run(v[j]);
 #pragma unroll
           for (int m = 0; m < F::R / 2; ++m) put<T, PASS_CONV>(&base[(b + m * F::NB) * rs], v[j][m]);
@@ -290,8 +309,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       // multiply, then the first inverse stage (span 1) in registers
 #pragma unroll
       for (int j = 0; j < Lf::J; ++j) {
+        const int b = q + NQ * j;
 #pragma unroll
-        for (int m = 0; m < Lf::R; ++m) w[j][m] = cscale(w[j][m], gv[j][m]);
+        for (int m = 0; m < Lf::R; ++m) multiply(w[j][m], gv[j][m], b + m * Lf::NB, upper_k1);
         Dft<Lf::R, true, T>::run(w[j]);
       }
       lds_barrier();
@@ -323,10 +343,10 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       if (e < twf_size(L, PID)) twl[e] = twr[i];
     }
   }
-  run_set(base_a, raw_a, cok);
+  run_set(out_a, raw_a, cok, false);
   if (gathered || two) {  // block-uniform: barriers inside
     lds_barrier();
-    run_set(base_b, raw_b, two);
+    run_set(out_b, raw_b, two, true);
   }
 }
 

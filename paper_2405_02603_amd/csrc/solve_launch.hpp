@@ -185,7 +185,9 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
     const dim3 grid((unsigned)(a.nouter * a.ntiles), (unsigned)items);                              \
     const dim3 block(c.tiles * c.nq);                                                               \
     if (kind == 2) {                                                                                \
-      if constexpr (conv_pipelined<T>(LV, VV)) {                                                    \
+      if (conv_pipelined<T>(LV, VV) && (a.comp != 0 || a.out[0])) {                                 \
+        return hipErrorInvalidValue; /* the pipelined kernel does the in-place potential only */   \
+      } else if constexpr (conv_pipelined<T>(LV, VV)) {                                             \
         ColArgs b = a;                                                                              \
         b.ntail = 0;                                                                                \
         const int nb = b.nouter * b.ntiles < CONV_PIPE_BLOCKS ? b.nouter * b.ntiles : CONV_PIPE_BLOCKS; \
@@ -284,6 +286,8 @@ struct SolveGeom {
   void* work[MAX_ITEMS];        // S of each item
   const void* rho[MAX_ITEMS];
   void* phi[MAX_ITEMS];
+  int comp;                     // P3 multiply: 0 potential, 1 + a derivative along axis a
+  void* work_out[MAX_ITEMS];    // P3 result and P4/P5 workspace (NULL: work, in place)
 };
 
 // Passes first..last of one solve (0 = P1 ... 4 = P5).
@@ -310,7 +314,11 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
   for (int i = 0; i < g.items; ++i) {
     cc.data[i] = g.work[i];
     cc.ghat[i] = g.ghat[i];
+    cc.out[i] = g.work_out[i];
   }
+  cc.comp = g.comp;
+  // P4 and P5 work on the P3 result
+  void* const* after = g.work_out[0] ? g.work_out : g.work;
   cc.ncols = g.n2 + 1;
   cc.row_stride = plane;
   cc.outer_stride = P;
@@ -344,13 +352,16 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
         ca.tw = g.tw_c1[1];
         return launch_col<T>(2 * g.n1, g.var[1], 0, ca, g.items, s);
       case 2: set_cols(cc, tc0, c0, c1); return launch_col<T>(2 * g.n0, g.var[2], 2, cc, g.items, s);
-      case 3:
-        set_cols(ca, tc4, c0, c1);
-        ca.tw = g.tw_c1[3];
-        return launch_col<T>(2 * g.n1, g.var[3], 1, ca, g.items, s);
+      case 3: {
+        ColArgs c4 = ca;
+        for (int i = 0; i < g.items; ++i) c4.data[i] = after[i];
+        set_cols(c4, tc4, c0, c1);
+        c4.tw = g.tw_c1[3];
+        return launch_col<T>(2 * g.n1, g.var[3], 1, c4, g.items, s);
+      }
       case 4:
         for (int i = 0; i < g.items; ++i) {
-          ra.in[i] = g.work[i];
+          ra.in[i] = after[i];
           ra.out[i] = g.phi[i];
         }
         ra.tw = g.tw_row[4];
@@ -359,6 +370,7 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
     }
   };
   hipError_t e = hipSuccess;
+  if (g.var[1] == FUSED && (g.comp != 0 || g.work_out[0])) return hipErrorInvalidValue;  // caller picks separate passes
   if (g.var[1] == FUSED) {
     // passes 1-3 as one fused kernel over column tiles: a range holds all of
     // them or none (pass 0 or pass 4 alone)

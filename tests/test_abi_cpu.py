@@ -164,3 +164,43 @@ def test_schedule_validation(lib):
     st, h = _create(lib, _desc(n=256))
     assert lib.fsp_plan_set_schedule(h, fused) == _lib.FSP_ERR_INVALID_ARG
     lib.fsp_plan_destroy(h)
+
+
+def test_gradient_plan_sizes_offsets_and_errors(lib):
+    # unknown flag bits are rejected
+    d = _desc(n=32)
+    d.flags = 2
+    assert _create(lib, d)[0] == _lib.FSP_ERR_INVALID_ARG
+    # a plan without FSP_WANT_GRAD: one octant, one workspace, no derivative tables
+    st, h0 = _create(lib, _desc(n=(16, 24, 32)))
+    g0, w0 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fsp_plan_bytes(h0, ctypes.byref(g0), ctypes.byref(w0)) == _lib.FSP_OK
+    off = ctypes.c_size_t()
+    assert lib.fsp_plan_octant_offset(h0, 1, ctypes.byref(off)) == _lib.FSP_ERR_INVALID_ARG
+    dummy = ctypes.c_void_p(256)
+    assert lib.fsp_solve_grad(h0, dummy, None, dummy, None) == _lib.FSP_ERR_INVALID_ARG
+    # with it: three more octants in the Green's buffer and a second spectrum in the workspace
+    d = _desc(n=(16, 24, 32))
+    d.flags = _lib.FSP_WANT_GRAD
+    st, h = _create(lib, d)
+    assert st == _lib.FSP_OK
+    g, w = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fsp_plan_bytes(h, ctypes.byref(g), ctypes.byref(w)) == _lib.FSP_OK
+    assert w.value == 2 * w0.value
+    layout_off = ctypes.c_size_t()
+    assert lib.fsp_plan_ghat_layout(h, ctypes.byref(layout_off), None) == _lib.FSP_OK
+    offs = []
+    for c in range(4):
+        assert lib.fsp_plan_octant_offset(h, c, ctypes.byref(off)) == _lib.FSP_OK
+        offs.append(off.value)
+    assert offs[0] == layout_off.value
+    step = offs[1] - offs[0]
+    assert step > 0 and step % 256 == 0 and offs[2] - offs[1] == step and offs[3] - offs[2] == step
+    assert g.value == offs[3] + step and g0.value == offs[0] + step
+    for bad in (-1, 4):
+        assert lib.fsp_plan_octant_offset(h, bad, ctypes.byref(off)) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_solve_grad(h, None, None, dummy, None) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_solve_grad(h, dummy, None, None, None) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_solve_grad(h, dummy, None, dummy, None) == _lib.FSP_ERR_NOT_READY
+    lib.fsp_plan_destroy(h)
+    lib.fsp_plan_destroy(h0)
