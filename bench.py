@@ -94,6 +94,7 @@ def parse(argv=None):
                     help="kept for older command lines: the 1 GiB device copy (counter calibration for "
                          "rocprofv3 --pmc) now always runs")
     ap.add_argument("--skip-f64", action="store_true")
+    ap.add_argument("--skip-extras", action="store_true", help="skip the gradient and precompute timings")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
     ap.add_argument("--workload", default="single", choices=["single", "batch", "serve"],
                     help="single: the 256^3 headline; batch: 64 uneven right-hand sides per graph launch; "
@@ -226,6 +227,58 @@ def direct_sum_timing():
         direct.convolve(rho, k, greens.spacing(n, lo, hi))
         el = time.perf_counter() - t0
     return {"seconds": round(el, 3), "threads": 1, "grid": "32^3 Hockney-Eastwood"}
+
+
+def time_calls(torch, fn, steps, warmup):
+    """Mean milliseconds of fn() on the current stream (HIP events around the loop)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def bench_grad(torch, W, n, lo, hi, src, args):
+    """phi and grad phi in one call (fsp_solve_grad), both precisions, same input as the headline."""
+    from paper_2405_02603_amd import Plan
+
+    out = {}
+    rho64 = W.source_density(n, lo, hi, src)
+    for prec in ("f32", "f64"):
+        dt = torch.float32 if prec == "f32" else torch.float64
+        plan = Plan(n=n, lo=lo, hi=hi, greens=args.greens, prec=prec, grad=True)
+        rho = torch.from_numpy(rho64).to(device="cuda", dtype=dt)
+        phi = torch.empty_like(rho)
+        grad = torch.empty((3,) + rho.shape, dtype=dt, device="cuda")
+        plan.autotune(rho, phi, reps=4)
+        ms = time_calls(torch, lambda: plan.solve_grad(rho, grad=grad, phi=phi), max(10, args.steps // 4), 5)
+        pb = pass_bytes((n, n, n), 4 if prec == "f32" else 8)
+        model = pb[0] + pb[1] + 4 * (pb[2] + pb[3] + pb[4])   # forward once, four axis-0 + inverse sets
+        out[prec] = {"ms": round(ms, 5), "model_bytes": model,
+                     "hbm_frac_model": round(model / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+        del plan, rho, phi, grad
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_precompute(torch, n, lo, hi):
+    """Milliseconds of fsp_precompute (float64 Green's tables) per kernel and precision."""
+    from paper_2405_02603_amd import Plan
+
+    out = {}
+    for greens in ("hockney", "vico_dct", "vico"):
+        for prec in ("f32",):
+            plan = Plan(n=n, lo=lo, hi=hi, greens=greens, prec=prec)
+            torch.cuda.synchronize()
+            out[greens] = round(time_calls(torch, plan.precompute, 3, 1), 3)
+            del plan
+            torch.cuda.empty_cache()
+    return out
 
 
 def bench_batch(args):
@@ -405,6 +458,13 @@ def main(argv=None):
         del plan, rho, phi
         torch.cuda.empty_cache()
 
+    # the gradient solve (phi and its three derivatives) and the Green's-table precompute
+    if not args.skip_extras:
+        extra["grad"] = bench_grad(torch, W, n, lo, hi, src, args)
+        for prec, r in extra["grad"].items():    # time of phi + grad over the time of phi alone
+            if prec in results:
+                r["vs_potential_only"] = round(r["ms"] / results[prec]["ms"], 3)
+        extra["precompute_ms"] = bench_precompute(torch, n, lo, hi)
     # a plain device copy of 1 GiB: the bandwidth a streaming kernel reaches on this GPU
     extra["copy_calibration"] = copy_calibration(torch)
 

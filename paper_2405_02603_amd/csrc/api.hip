@@ -26,8 +26,8 @@ hipError_t greens_he_kernel(double* K, const int n[3], const double h[3], double
 hipError_t greens_he_grad_kernel(double* D, const int n[3], const double h[3], int axis, hipStream_t s);
 hipError_t greens_vico_spectrum(double* G, const int samples[3], const double f[3], double L, bool fft_order,
                                 hipStream_t s);
-hipError_t greens_contract(const double* X, double* Y, const double* C, int nout, int nin, long long rest,
-                           hipStream_t s);
+hipError_t greens_contract_axis(const double* X, double* Y, const double* C, const long long dims[3], int axis,
+                                int nout, hipStream_t s);
 hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int tile, double scale,
                                hipStream_t s);
 int conv_tile_f32(int L);
@@ -112,29 +112,43 @@ void append_full_twiddles(std::vector<char>& buf, int L, int pid) {
   }
 }
 
+// cos and sin of pi j / half for j in [0, 2 half): every matrix entry below
+// has an angle pi t / half with t an exact integer reduced mod 2 half, so one
+// long-double table per matrix replaces a trigonometric call per entry.
+struct TrigTable {
+  std::vector<long double> c, s;
+  explicit TrigTable(int half) : c(2 * (size_t)half), s(2 * (size_t)half) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int j = 0; j < 2 * half; ++j) {
+      c[j] = cosl(pi * (long double)j / (long double)half);
+      s[j] = sinl(pi * (long double)j / (long double)half);
+    }
+  }
+};
+
 // DCT-I rows m < nout of a length period+1 transform: C[m][l] = w_l cos(pi l m / period),
 // w_0 = w_period = 1, else 2.
 void dct1_matrix(std::vector<double>& C, int nout, int period) {
   const int nin = period + 1;
-  const long double pi = 3.141592653589793238462643383279502884L;
+  const TrigTable tt(period);
   C.resize((size_t)nout * nin);
   for (int m = 0; m < nout; ++m)
     for (int l = 0; l < nin; ++l) {
       const long long t = ((long long)l * m) % (2LL * period);
       const long double w = (l == 0 || l == period) ? 1.0L : 2.0L;
-      C[(size_t)m * nin + l] = (double)(w * cosl(pi * (long double)t / (long double)period));
+      C[(size_t)m * nin + l] = (double)(w * tt.c[t]);
     }
 }
 
 // Octant rows of the inverse DFT of real, even data on a grid of s = 4n points:
 // C[m][l] = cos(2 pi l m / s), m <= n.
 void dft_cos_matrix(std::vector<double>& C, int nout, int s) {
-  const long double pi = 3.141592653589793238462643383279502884L;
+  const TrigTable tt(s / 2);  // 2 pi t / s = pi t / (s / 2), s even
   C.resize((size_t)nout * s);
   for (int m = 0; m < nout; ++m)
     for (int l = 0; l < s; ++l) {
       const long long t = ((long long)l * m) % s;
-      C[(size_t)m * s + l] = (double)cosl(2.0L * pi * (long double)t / (long double)s);
+      C[(size_t)m * s + l] = (double)tt.c[t];
     }
 }
 
@@ -143,38 +157,38 @@ void dft_cos_matrix(std::vector<double>& C, int nout, int s) {
 // transform along that axis: C[m][l] = 2 (-kfac l) sin(pi l m / period)
 // (the end samples carry sin = 0).
 void sine_k_matrix(std::vector<double>& C, int nout, int period, double kfac) {
-  const long double pi = 3.141592653589793238462643383279502884L;
   const int nin = period + 1;
+  const TrigTable tt(period);
   C.assign((size_t)nout * nin, 0.0);
   for (int m = 0; m < nout; ++m)
     for (int l = 1; l < period; ++l) {
       const long long t = ((long long)l * m) % (2LL * period);
-      C[(size_t)m * nin + l] = (double)(-2.0L * kfac * l * sinl(pi * (long double)t / (long double)period));
+      C[(size_t)m * nin + l] = (double)(-2.0L * kfac * l * tt.s[t]);
     }
 }
 
 // The same on the full grid of s samples in FFT order (signed frequency
 // l' = l or l - s): C[m][l] = -(kfac l') sin(2 pi l m / s).
 void dft_sin_k_matrix(std::vector<double>& C, int nout, int s, double kfac) {
-  const long double pi = 3.141592653589793238462643383279502884L;
+  const TrigTable tt(s / 2);
   C.resize((size_t)nout * s);
   for (int m = 0; m < nout; ++m)
     for (int l = 0; l < s; ++l) {
       const long long t = ((long long)l * m) % s;
       const long long ls = l < s / 2 ? l : l - s;
-      C[(size_t)m * s + l] = (double)(-(long double)kfac * ls * sinl(2.0L * pi * (long double)t / (long double)s));
+      C[(size_t)m * s + l] = (double)(-(long double)kfac * ls * tt.s[t]);
     }
 }
 
 // Sine transform of an odd table on [0, n] (0 at both ends), the transform of
 // its odd extension to 2n points up to a factor -i: C[k][m] = 2 sin(pi k m / n).
 void dst1_matrix(std::vector<double>& C, int n) {
-  const long double pi = 3.141592653589793238462643383279502884L;
+  const TrigTable tt(n);
   C.assign((size_t)(n + 1) * (n + 1), 0.0);
   for (int k = 0; k <= n; ++k)
     for (int m = 1; m < n; ++m) {
       const long long t = ((long long)k * m) % (2LL * n);
-      C[(size_t)k * (n + 1) + m] = (double)(2.0L * sinl(pi * (long double)t / (long double)n));
+      C[(size_t)k * (n + 1) + m] = (double)(2.0L * tt.s[t]);
     }
 }
 
@@ -578,14 +592,13 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
     double scale = p->V / (8.0 * n0 * n1 * n2);  // folds V and the 1/M^3 of the inverse transform
     double* X = A;
     double* Y = B;
+    int axis = 0;
     auto contract = [&](int nout) {
-      // leading axis dims[0] -> nout, rotated to the back
-      const long long rest = dims[1] * dims[2];
-      if (e == hipSuccess) e = fsp::greens_contract(X, Y, C + moff[mi], nout, (int)dims[0], rest, s);
+      // axes in order 0, 1, 2: dims[axis] -> nout, layout order unchanged
+      if (e == hipSuccess) e = fsp::greens_contract_axis(X, Y, C + moff[mi], dims, axis, nout, s);
       ++mi;
-      dims[0] = dims[1];
-      dims[1] = dims[2];
-      dims[2] = nout;
+      dims[axis] = nout;
+      axis = (axis + 1) % 3;
       std::swap(X, Y);
     };
     if (gk == FSP_HOCKNEY) {
@@ -775,8 +788,7 @@ fsp_status fsp_solve_grad(fsp_plan p, const void* rho, void* phi, void* grad, vo
   int var[5];
   for (int i = 0; i < 5; ++i) var[i] = p->var[i];
   if (var[1] == fsp::FUSED) var[1] = var[2] = var[3] = 0;
-  if (f64 ? fsp::conv_pipelined<double>(2 * p->n[0], var[2]) : fsp::conv_pipelined<float>(2 * p->n[0], var[2]))
-    var[2] = 0;
+  if (var[2] == 2) var[2] = 0;  // the derivative multiply is instantiated for axis-0 variants 0 and 1
   fsp::SolveGeom g = group_geom(p, var);
   add_item(g, p, rho, nullptr);
   e = run_group(g, f64, 0, 1, s);  // the forward transforms along axes 2 and 1, once

@@ -21,10 +21,14 @@
 // spectrum, and a sine transform of the odd extension on the doubled grid,
 // whose transform is -i times the stored real octant.
 //
-// Each one-axis transform is a dense contraction of the leading axis with a
-// small cosine matrix that also rotates the axes, Y[rest][m] = sum_l C[m][l]
-// X[l][rest]: after three of them the data are back in [m0][m1][m2] order.
+// Each one-axis transform is a dense contraction of one axis with a small
+// cosine (or sine) matrix, C[m][l] applied along that axis with the other axes
+// in place -- a float64 GEMM, done by rocBLAS.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <map>
+#include <mutex>
 
 namespace fsp {
 
@@ -89,58 +93,6 @@ __global__ __launch_bounds__(256) void k_vico_spectrum(double* G, int s0, int s1
   G[i] = v;
 }
 
-// Y[r * nout + m] = sum_{l < nin} C[m * nin + l] * X[l * rest + r]
-// 64 x 64 output tile per 256-thread block, 16-deep slices of l through LDS.
-__global__ __launch_bounds__(256) void k_contract_rotate(const double* __restrict__ X, double* __restrict__ Y,
-                                                         const double* __restrict__ C, int nout, int nin,
-                                                         long long rest) {
-  constexpr int BM = 64, BR = 64, BK = 16;
-  __shared__ double sC[BK][BM + 1];
-  __shared__ double sX[BK][BR + 1];
-  const int tid = threadIdx.x;
-  const int tm = tid % 16, tr = tid / 16;
-  const int m0 = blockIdx.y * BM;
-  const long long r0 = (long long)blockIdx.x * BR;
-  double acc[4][4] = {};
-  for (int l0 = 0; l0 < nin; l0 += BK) {
-    for (int e = tid; e < BM * BK; e += 256) {
-      const int mm = e / BK, ll = e % BK;
-      const int m = m0 + mm, l = l0 + ll;
-      sC[ll][mm] = (m < nout && l < nin) ? C[(long long)m * nin + l] : 0.0;
-    }
-    for (int e = tid; e < BK * BR; e += 256) {
-      const int ll = e / BR, rr = e % BR;
-      const int l = l0 + ll;
-      const long long r = r0 + rr;
-      sX[ll][rr] = (l < nin && r < rest) ? X[(long long)l * rest + r] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ll = 0; ll < BK; ++ll) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = sC[ll][tm + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = sX[ll][tr + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const long long r = r0 + tr + 16 * j;
-    if (r >= rest) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int m = m0 + tm + 16 * i;
-      if (m < nout) Y[r * nout + m] = acc[i][j];
-    }
-  }
-}
-
 // Store the octant G[k0][k1][k2] (float64, dense) scaled, in the blocked layout
 // out[((k1 * tiles + k2 / tile) * (n0 + 1) + k0) * tile + k2 % tile]; slots of
 // the last tile beyond k2 = n2 are zero.
@@ -185,11 +137,49 @@ hipError_t greens_vico_spectrum(double* G, const int samples[3], const double f[
   return hipGetLastError();
 }
 
-hipError_t greens_contract(const double* X, double* Y, const double* C, int nout, int nin, long long rest,
-                           hipStream_t s) {
-  const dim3 grid((unsigned)((rest + 63) / 64), (unsigned)((nout + 63) / 64));
-  hipLaunchKernelGGL(k_contract_rotate, grid, dim3(256), 0, s, X, Y, C, nout, nin, rest);
-  return hipGetLastError();
+// One rocBLAS handle per device for the life of the process (created on first use).
+static rocblas_handle blas_handle(int dev) {
+  static std::mutex mu;
+  static std::map<int, rocblas_handle> handles;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = handles.find(dev);
+  if (it != handles.end()) return it->second;
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+  handles[dev] = h;
+  return h;
+}
+
+// Contract axis `axis` of the row-major array X[d0][d1][d2] with the matrix
+// C[nout][d_axis] (row-major): Y has the same axis order with d_axis -> nout.
+// Each case is one float64 GEMM in column-major terms (rocBLAS):
+//   axis 0: Y (d1 d2 x nout) = X (d1 d2 x d0) C^T-as-stored (d0 x nout)
+//   axis 1: per i0, Y_i0 (d2 x nout) = X_i0 (d2 x d1) C (d1 x nout)  (strided batch over i0)
+//   axis 2: Y (nout x d0 d1) = C^T (nout x d2) X (d2 x d0 d1)
+hipError_t greens_contract_axis(const double* X, double* Y, const double* C, const long long dims[3], int axis,
+                                int nout, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  rocblas_handle h = blas_handle(dev);
+  if (!h || rocblas_set_stream(h, s) != rocblas_status_success) return hipErrorInvalidValue;
+  const long long d0 = dims[0], d1 = dims[1], d2 = dims[2];
+  if (d0 * d1 > 0x7fffffffLL || d1 * d2 > 0x7fffffffLL) return hipErrorInvalidValue;
+  const double one = 1.0, zero = 0.0;
+  rocblas_status st;
+  const rocblas_operation N = rocblas_operation_none, T = rocblas_operation_transpose;
+  if (axis == 0) {
+    const rocblas_int m = (rocblas_int)(d1 * d2);
+    st = rocblas_dgemm(h, N, N, m, nout, (rocblas_int)d0, &one, X, m, C, (rocblas_int)d0, &zero, Y, m);
+  } else if (axis == 1) {
+    st = rocblas_dgemm_strided_batched(h, N, N, (rocblas_int)d2, nout, (rocblas_int)d1, &one, X, (rocblas_int)d2,
+                                       (rocblas_stride)(d1 * d2), C, (rocblas_int)d1, 0, &zero, Y, (rocblas_int)d2,
+                                       (rocblas_stride)nout * d2, (rocblas_int)d0);
+  } else {
+    st = rocblas_dgemm(h, T, N, nout, (rocblas_int)(d0 * d1), (rocblas_int)d2, &one, C, (rocblas_int)d2, X,
+                       (rocblas_int)d2, &zero, Y, nout);
+  }
+  return st == rocblas_status_success ? hipSuccess : hipErrorLaunchFailure;
 }
 
 hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int tile, double scale,

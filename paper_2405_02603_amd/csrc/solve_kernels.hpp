@@ -51,7 +51,7 @@ struct ColArgs {
   int ntail;                  // P3: leading blocks that gather column ncols - 1 over TC k1 pairs
   int gather_min;             // P3 (host side): grid size from which the launcher gathers
   int comp;                   // P3: 0 potential (real multiply); 1 + a derivative along axis a
-  void* out[MAX_ITEMS];       // P3: result spectrum of each item (NULL: in place in data)
+  void* out[MAX_ITEMS];       // P3 derivative: result spectrum of each item (else in place in data)
 };
 
 struct RowArgs {
@@ -179,7 +179,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
 // the table values of their forward butterflies once, for both sets.
 // TWF: the plan's complete twiddle table is read into LDS once per block, so
 // the butterflies load every power instead of multiplying it out of six.
-template <typename T, int L, int PID, int TC, int NQ, bool TWF = false>
+// GRAD: the multiply of a derivative table (a.comp) and the result written to
+// a.out; a separate instantiation, so the potential's kernel carries none of it.
+template <typename T, int L, int PID, int TC, int NQ, bool TWF = false, bool GRAD = false>
 __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   constexpr int K = plan_len(L, PID);
   static_assert(!TWF || K > 1, "single-stage plans have no twiddles");
@@ -251,18 +253,21 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   const bool two = cok && !(p == 0 || p == a.n1);
   cx<T>* base_a = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)p * a.outer_stride + col;
   cx<T>* base_b = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)(2 * a.n1 - p) * a.outer_stride + col;
-  cx<T>* obase = reinterpret_cast<cx<T>*>(a.out[blockIdx.y] ? a.out[blockIdx.y] : a.data[blockIdx.y]);
-  cx<T>* out_a = obase + (long long)p * a.outer_stride + col;
-  cx<T>* out_b = obase + (long long)(2 * a.n1 - p) * a.outer_stride + col;
+  cx<T>* out_a = base_a;
+  cx<T>* out_b = base_b;
+  if constexpr (GRAD) {
+    cx<T>* obase = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]);
+    out_a = obase + (long long)p * a.outer_stride + col;
+    out_b = obase + (long long)(2 * a.n1 - p) * a.outer_stride + col;
+  }
   // The derivative tables are odd along their axis: their transform is -i T with
   // the real octant T read at the folded frequency and negated on the upper half
   // of that axis (k0 > n0; for axis 1 the partner 2 n1 - p; axis 2 holds k2 <= n2).
-  const int comp = a.comp;
   auto multiply = [&](cx<T>& w, T g, int k0, bool upper_k1) {
-    if (comp == 0) {
+    if constexpr (!GRAD) {
       w = cscale(w, g);
     } else {
-      const bool neg = comp == 1 ? (k0 > L / 2) : (comp == 2 && upper_k1);
+      const bool neg = a.comp == 1 ? (k0 > L / 2) : (a.comp == 2 && upper_k1);
       const T t = neg ? -g : g;
       w = cx<T>{t * w.y, -t * w.x};  // w * (-i t)
     }

@@ -185,8 +185,16 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
     const dim3 grid((unsigned)(a.nouter * a.ntiles), (unsigned)items);                              \
     const dim3 block(c.tiles * c.nq);                                                               \
     if (kind == 2) {                                                                                \
-      if (conv_pipelined<T>(LV, VV) && (a.comp != 0 || a.out[0])) {                                 \
-        return hipErrorInvalidValue; /* the pipelined kernel does the in-place potential only */   \
+      if (a.comp != 0) {                                                                            \
+        /* a derivative table: variants 0 and 1 have an instantiation for it */                    \
+        if constexpr (VV < 2) {                                                                     \
+          const ColArgs b = conv_gather(a, c.tiles);                                                \
+          hipLaunchKernelGGL((k_col_conv<T, LV, c.pid, c.tiles, c.nq, false, true>),                \
+                             dim3((unsigned)(b.nouter * b.ntiles + b.ntail), (unsigned)items),      \
+                             block, 0, s, b);                                                       \
+        } else {                                                                                    \
+          return hipErrorInvalidValue;                                                              \
+        }                                                                                           \
       } else if constexpr (conv_pipelined<T>(LV, VV)) {                                             \
         ColArgs b = a;                                                                              \
         b.ntail = 0;                                                                                \
@@ -287,7 +295,7 @@ struct SolveGeom {
   const void* rho[MAX_ITEMS];
   void* phi[MAX_ITEMS];
   int comp;                     // P3 multiply: 0 potential, 1 + a derivative along axis a
-  void* work_out[MAX_ITEMS];    // P3 result and P4/P5 workspace (NULL: work, in place)
+  void* work_out[MAX_ITEMS];    // derivatives: P3 result and P4/P5 workspace (potential: NULL, in place)
 };
 
 // Passes first..last of one solve (0 = P1 ... 4 = P5).
@@ -370,7 +378,8 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
     }
   };
   hipError_t e = hipSuccess;
-  if (g.var[1] == FUSED && (g.comp != 0 || g.work_out[0])) return hipErrorInvalidValue;  // caller picks separate passes
+  if (g.var[1] == FUSED && g.comp != 0) return hipErrorInvalidValue;  // the caller picks separate passes
+  if (g.comp != 0 && !g.work_out[0]) return hipErrorInvalidValue;     // derivatives are written out of place
   if (g.var[1] == FUSED) {
     // passes 1-3 as one fused kernel over column tiles: a range holds all of
     // them or none (pass 0 or pass 4 alone)
