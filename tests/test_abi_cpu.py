@@ -204,3 +204,25 @@ def test_gradient_plan_sizes_offsets_and_errors(lib):
     assert lib.fsp_solve_grad(h, dummy, None, dummy, None) == _lib.FSP_ERR_NOT_READY
     lib.fsp_plan_destroy(h)
     lib.fsp_plan_destroy(h0)
+
+
+@pytest.mark.parametrize("n", [64, 128, 256, 512])
+def test_footprint_against_the_paper_accounting(lib, n):
+    """Device bytes of one float64 solve here (Green's buffer, workspace, rho and phi) beside the
+    field memory of Section 3.3 (five float64 fields on the doubled grid and more): the fused
+    pad/crop and the real octant keep it below a third of the paper's smallest (modified
+    Vico-Greengard) figure, and the transient precompute of the Vico-Greengard tables stays
+    below the (2N+1)^3 field the paper keeps."""
+    from oracle import memory
+    for greens, paper in ((0, memory.hockney_bytes(n)), (2, memory.vico_dct_bytes(n))):
+        st, h = _create(lib, _desc(n=n, greens=greens, prec=1, lo=-1.0, hi=1.0))
+        assert st == _lib.FSP_OK
+        g, w = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lib.fsp_plan_bytes(h, ctypes.byref(g), ctypes.byref(w)) == _lib.FSP_OK
+        ours = g.value + w.value + 2 * n ** 3 * 8
+        assert ours < paper / 3, (greens, ours, paper)
+        pb = ctypes.c_size_t()
+        assert lib.fsp_plan_precompute_bytes(h, ctypes.byref(pb)) == _lib.FSP_OK
+        if greens == 2:
+            assert pb.value < 2 * (2 * n + 1) ** 3 * 8
+        lib.fsp_plan_destroy(h)

@@ -11,6 +11,7 @@
 * 512^3: sampled outputs of the direct sum (Hockney-Eastwood, whose kernel table
   is closed-form) and, for Vico-Greengard, the closed-form potential on a strided
   subgrid of the result.
+* The non-smooth uniform ball of Section 3.1: about second order for both kernels.
 """
 import numpy as np
 import pytest
@@ -164,3 +165,26 @@ def test_full_size_512(torch_cuda, box):
         print("full 512", box[1], prec, f"vico vs closed form {e:.3e}")
         assert e <= tol_cf, (prec, e)
         del phi
+
+
+def test_sphere_source_second_order_both_kernels(torch_cuda):
+    """The uniform ball of Section 3.1 (radius 1, density 2, centred, box [-1.2, 1.2]^3): its
+    density jumps at the surface, so both kernels converge at about second order, Vico-Greengard
+    no longer spectrally; the GPU float64 errors equal the oracle's at the small sizes."""
+    torch = torch_cuda
+    lo, hi = (-1.2,) * 3, (1.2,) * 3
+    sizes = (24, 32, 48, 64, 96, 128)
+    err = {}
+    for kind in ("hockney", "vico_dct"):
+        for n in sizes:
+            rho = W.sphere_density(n, lo, hi, (0.0, 0.0, 0.0), 1.0, 2.0)
+            closed = exact.sphere_potential(n, lo, hi, (0.0, 0.0, 0.0), 1.0, 2.0)
+            phi = _solve(torch, n, (lo, hi), kind, "f64", rho)
+            if n <= 48:
+                assert rel_l2(phi, reference(rho, kind, lo, hi, use_direct=False)) <= F64_TOL
+            err[(kind, n)] = rel_l2(phi, closed)
+        slope = -np.polyfit(np.log([float(n) for n in sizes]), np.log([err[(kind, n)] for n in sizes]), 1)[0]
+        print("sphere", kind, f"order {slope:.2f}", {n: f"{err[(kind, n)]:.2e}" for n in sizes})
+        assert 1.5 < slope < 3.0, (kind, slope)
+    for n in sizes:   # the spectral kernel gains little on a non-smooth source
+        assert err[("vico_dct", n)] / err[("hockney", n)] > 0.2
