@@ -1,7 +1,8 @@
 """Benchmark: Vico-Greengard free-space Poisson solves of a 256^3 grid on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--greens vico_dct]
-                    [--no-cpu-baseline] [--cpu-seconds 20] [--copy-calibration]
+                    [--no-cpu-baseline] [--cpu-seconds 20] [--skip-f64] [--skip-extras]
+                    [--workload single|batch|serve]
 
 A step is one full solve (all five passes: axis-2 real transform with the zero
 padding fused, axis-1 forward, axis-0 forward + Green's multiply + inverse,
@@ -17,6 +18,8 @@ float64 CPU oracle.  ``roofline`` is the dominant kernel's algorithmic bytes per
 launch over its average launch time (HIP events around that kernel inside a
 timed loop, on the stream it runs on) against the 8 TB/s HBM peak.
 ``cpu_baseline`` times the oracle (float64 FFT route, scipy) on the host.
+``grad`` times phi with its gradient (fsp_solve_grad) and ``precompute_ms`` the
+float64 Green's-table refresh of each kernel (outside the headline).
 """
 from __future__ import annotations
 

@@ -115,9 +115,13 @@ fsp_status fsp_plan_share_ghat(fsp_plan dst, fsp_plan src);
 
 /* Compute the transform of the Green's function on the device, in float64,
  * and store it (rounded once to the solve precision) in the plan's Green's
- * buffer, with the plan's twiddle tables.  Asynchronous on `stream`;
- * allocates and frees a transient float64 buffer of
- * fsp_plan_precompute_bytes bytes.  Calling it again recomputes. */
+ * buffer, with the plan's twiddle tables (and, with FSP_WANT_GRAD, the three
+ * derivative tables).  The per-axis cosine/sine contractions are float64
+ * GEMMs run by rocBLAS; the first call on a device creates that device's
+ * rocBLAS handle, kept until the process ends.  Asynchronous on `stream`;
+ * allocates and frees transient float64 buffers of fsp_plan_precompute_bytes
+ * bytes in stream order.  Calling it again recomputes (a refresh).
+ * FSP_ERR_OUT_OF_MEMORY if the transient buffers cannot be allocated. */
 fsp_status fsp_precompute(fsp_plan p, void* stream);
 
 /* phi = the free-space solution for rho (both device arrays, [n0][n1][n2] in
