@@ -269,6 +269,27 @@ def bench_grad(torch, W, n, lo, hi, src, args):
     return out
 
 
+def bench_large(torch, W, n, lo, hi, args):
+    """The 512^3 single solve (same box and 8-Gaussian source), both precisions, autotuned."""
+    from paper_2405_02603_amd import Plan
+
+    rho64 = W.source_density(n, lo, hi, W.multiblob(seed=3, count=8))
+    out = {}
+    for prec in ("f32", "f64"):
+        dt = torch.float32 if prec == "f32" else torch.float64
+        plan = Plan(n=n, lo=lo, hi=hi, greens=args.greens, prec=prec)
+        rho = torch.from_numpy(rho64).to(device="cuda", dtype=dt)
+        phi = torch.empty_like(rho)
+        plan.autotune(rho, phi, reps=2)
+        ms = time_calls(torch, lambda: plan.solve(rho, phi), 20, 3)
+        out[prec] = {"ms": round(ms, 4), "solves_per_s": round(1e3 / ms, 2),
+                     "hbm_frac_model": round(plan.model_bytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                     "schedule": plan.schedule}
+        del plan, rho, phi
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_precompute(torch, n, lo, hi):
     """Milliseconds of fsp_precompute (float64 Green's tables) per kernel and precision."""
     from paper_2405_02603_amd import Plan
@@ -468,6 +489,8 @@ def main(argv=None):
             if prec in results:
                 r["vs_potential_only"] = round(r["ms"] / results[prec]["ms"], 3)
         extra["precompute_ms"] = bench_precompute(torch, n, lo, hi)
+        if n == 256:
+            extra["n512"] = bench_large(torch, W, 512, lo, hi, args)
     # a plain device copy of 1 GiB: the bandwidth a streaming kernel reaches on this GPU
     extra["copy_calibration"] = copy_calibration(torch)
 
