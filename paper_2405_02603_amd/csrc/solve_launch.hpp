@@ -25,7 +25,7 @@ __host__ __device__ constexpr int col_tc(int L) {
     case 32: return 32;
     case 64: case 96: case 128: return d ? 16 : 32;
     case 192: case 256: case 384: case 512: return d ? 8 : 16;
-    case 768: case 1024: return d ? 4 : 8;
+    case 768: case 1024: return d ? 8 : 16;  // 128-byte row segments, as for 192-512
     default: return 0;
   }
 }
@@ -34,8 +34,9 @@ __host__ __device__ constexpr int col_tc(int L) {
 template <typename T>
 __host__ __device__ constexpr TileCfg col_cfg(int L, int v) {
   const int tc = col_tc<T>(L);
-  // wider tiles (longer row segments, more LDS) for variant 2 of the long pencils;
-  // the axis-0 pass never uses this shape (its variant 2 is the pipelined kernel)
+  // wider tiles (longer row segments, more LDS) for variant 2 of lengths 256-512;
+  // the axis-0 pass never uses this shape (its variant 2 is the LDS-table or
+  // the pipelined kernel)
   const int tw = 2 * tc;
   switch (L) {
     case 16: return v == 0 ? TileCfg{0, tc, 1} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{1, tc, 2};
@@ -49,8 +50,10 @@ __host__ __device__ constexpr TileCfg col_cfg(int L, int v) {
     case 256: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tw, 16};
     case 384: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 8} : TileCfg{0, tw, 8};
     case 512: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tw, 16};
-    case 768: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 16} : TileCfg{0, tw, 16};
-    case 1024: return v == 0 ? TileCfg{0, tc, 32} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tw, 32};
+    // one block per compute unit at these lengths (L * TC complex of LDS): variant 2
+    // adds threads per pencil instead of columns
+    case 768: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 16} : TileCfg{0, tc, 32};
+    case 1024: return v == 0 ? TileCfg{0, tc, 32} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{1, tc, 64};
     default: return {0, 0, 0};
   }
 }
@@ -79,17 +82,21 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
 
 // Axis-0 pass variants: variants 0 and 1 as col_cfg; variant 2 keeps the
 // complete twiddle table in LDS, with the shape of variant 0 (else 1) when the
-// table and the pencils fit in half of a compute unit's LDS, else it is the
-// pipelined persistent kernel (grid of at most CONV_PIPE_BLOCKS blocks) with
-// the shape of variant 1.
+// table costs no resident block (conv_twf_fits), else it is the pipelined
+// persistent kernel (grid of at most CONV_PIPE_BLOCKS blocks) with the shape
+// of variant 1.
 constexpr int CONV_PIPE_BLOCKS = 1024;
 constexpr int CONV_GATHER_MIN_BLOCKS = 2048;
-constexpr int CONV_TWF_LDS = 81920;
+constexpr int CONV_LDS_PER_CU = 163840;
 
+// The table may not cost a resident block: as many blocks of the variant fit
+// in a compute unit's LDS with it as without it.
 template <typename T>
 __host__ __device__ constexpr bool conv_twf_fits(int L, int v) {
   const TileCfg c = col_cfg<T>(L, v);
-  return plan_len(L, c.pid) > 1 && (L * c.tiles + twf_size(L, c.pid)) * 2 * (int)sizeof(T) <= CONV_TWF_LDS;
+  const int base = L * c.tiles * 2 * (int)sizeof(T);
+  const int with = base + twf_size(L, c.pid) * 2 * (int)sizeof(T);
+  return plan_len(L, c.pid) > 1 && with <= CONV_LDS_PER_CU && CONV_LDS_PER_CU / with == CONV_LDS_PER_CU / base;
 }
 
 template <typename T>
