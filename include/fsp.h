@@ -117,8 +117,9 @@ fsp_status fsp_plan_share_ghat(fsp_plan dst, fsp_plan src);
  * and store it (rounded once to the solve precision) in the plan's Green's
  * buffer, with the plan's twiddle tables (and, with FSP_WANT_GRAD, the three
  * derivative tables).  The per-axis cosine/sine contractions are float64
- * GEMMs run by rocBLAS; the first call on a device creates that device's
- * rocBLAS handle, kept until the process ends.  Asynchronous on `stream`;
+ * GEMMs run by rocBLAS; the first call from a host thread on a device
+ * creates a rocBLAS handle for that thread and device, kept until the thread
+ * ends.  Asynchronous on `stream`;
  * allocates and frees transient float64 buffers of fsp_plan_precompute_bytes
  * bytes in stream order.  Calling it again recomputes (a refresh).
  * FSP_ERR_OUT_OF_MEMORY if the transient buffers cannot be allocated. */

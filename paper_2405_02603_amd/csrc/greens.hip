@@ -28,7 +28,6 @@
 #include <rocblas/rocblas.h>
 
 #include <map>
-#include <mutex>
 
 namespace fsp {
 
@@ -137,16 +136,23 @@ hipError_t greens_vico_spectrum(double* G, const int samples[3], const double f[
   return hipGetLastError();
 }
 
-// One rocBLAS handle per device for the life of the process (created on first use).
+// rocBLAS handles of the calling host thread, one per device (created on first
+// use, destroyed when the thread ends): a handle carries its stream, so
+// threads that precompute at the same time each use their own.
+struct BlasHandles {
+  std::map<int, rocblas_handle> h;
+  ~BlasHandles() {
+    for (auto& kv : h) (void)rocblas_destroy_handle(kv.second);
+  }
+};
+
 static rocblas_handle blas_handle(int dev) {
-  static std::mutex mu;
-  static std::map<int, rocblas_handle> handles;
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = handles.find(dev);
-  if (it != handles.end()) return it->second;
+  static thread_local BlasHandles handles;
+  auto it = handles.h.find(dev);
+  if (it != handles.h.end()) return it->second;
   rocblas_handle h = nullptr;
   if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
-  handles[dev] = h;
+  handles.h[dev] = h;
   return h;
 }
 

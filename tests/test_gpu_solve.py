@@ -250,3 +250,39 @@ def test_column_chunks_and_gathered_column(torch_cuda, prec, tol, chunks, gather
             phi = plan.solve(to_dev(rho, dt))
             torch.cuda.synchronize()
             assert rel_l2(to_host(phi), reference(rho, "vico_dct", lo, hi, use_direct=False)) <= tol, (n, v)
+
+
+def test_precompute_from_two_threads(torch_cuda):
+    """Two host threads precompute at the same time (each on its own stream): the stored
+    transforms equal those of sequential precomputes."""
+    import threading
+    from paper_2405_02603_amd import Plan
+    torch = torch_cuda
+    cases = [((48, 32, 64), "vico_dct"), ((32, 64, 48), "hockney")]
+    want = []
+    for n, kind in cases:
+        p = Plan(n=n, lo=(-1.0,) * 3, hi=(1.0,) * 3, greens=kind, prec="f64")
+        torch.cuda.synchronize()
+        want.append(to_host(p.ghat_octant()))
+    got = [None, None]
+    errors = []
+
+    def work(i):
+        try:
+            n, kind = cases[i]
+            s = torch.cuda.Stream()
+            for _ in range(3):
+                p = Plan(n=n, lo=(-1.0,) * 3, hi=(1.0,) * 3, greens=kind, prec="f64", stream=s)
+                s.synchronize()
+            got[i] = to_host(p.ghat_octant())
+        except Exception as e:  # reported below, on the test's thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for g, w in zip(got, want):
+        assert np.max(np.abs(g - w)) <= 1e-15 * np.max(np.abs(w))
