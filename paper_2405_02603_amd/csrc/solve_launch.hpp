@@ -75,7 +75,8 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
     case 192: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 4} : TileCfg{0, 8, 16};
     case 256: return v == 0 ? TileCfg{0, d ? 8 : 16, 16} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{0, d ? 4 : 8, 16};
     case 384: return v == 0 ? TileCfg{0, d ? 4 : 8, 8} : v == 1 ? TileCfg{1, 8, 8} : TileCfg{0, 4, 16};
-    case 512: return v == 0 ? TileCfg{0, d ? 4 : 8, 16} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{0, d ? 8 : 16, 16};
+    // 512: the three-stage plan; 64 threads per row over 4 rows keeps 8 waves per SIMD
+    case 512: return v == 0 ? TileCfg{1, 4, 64} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{1, 16, 32};
     default: return {0, 0, 0};
   }
 }
