@@ -47,6 +47,17 @@ def pass_bytes(n, rb):
     return [real + half1, half1 + half2, 2 * half2 + octant, half2 + half1, half1 + real]
 
 
+def grad_bytes(n, rb):
+    """Algorithmic HBM bytes of phi and grad phi in one call: the forward passes
+    once, one axis-0 pass that reads the spectrum once and writes four (with four
+    tables), and the two inverse passes for each of the four outputs."""
+    pb = pass_bytes(n, rb)
+    n0, n1, n2 = n
+    half2 = n0 * 2 * n1 * (n2 + 1) * 2 * rb
+    octant = (n0 + 1) * (n1 + 1) * (n2 + 1) * rb
+    return pb[0] + pb[1] + half2 + 4 * (half2 + octant) + 4 * (pb[3] + pb[4])
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_vico_dct_256.txt")
 
 
@@ -260,8 +271,7 @@ def bench_grad(torch, W, n, lo, hi, src, args):
         grad = torch.empty((3,) + rho.shape, dtype=dt, device="cuda")
         plan.autotune(rho, phi, reps=4)
         ms = time_calls(torch, lambda: plan.solve_grad(rho, grad=grad, phi=phi), max(10, args.steps // 4), 5)
-        pb = pass_bytes((n, n, n), 4 if prec == "f32" else 8)
-        model = pb[0] + pb[1] + 4 * (pb[2] + pb[3] + pb[4])   # forward once, four axis-0 + inverse sets
+        model = grad_bytes((n, n, n), 4 if prec == "f32" else 8)
         out[prec] = {"ms": round(ms, 5), "model_bytes": model,
                      "hbm_frac_model": round(model / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
         del plan, rho, phi, grad

@@ -70,7 +70,7 @@ typedef enum { FSP_F32 = 0, FSP_F64 = 1 } fsp_prec;
 #define FSP_FLAG_NONE 0u
 /* Also precompute the derivative tables of the Green's function (three more
  * octants in the Green's buffer) and size the workspace for fsp_solve_grad
- * (two spectra instead of one). */
+ * (four spectra instead of one). */
 #define FSP_WANT_GRAD 1u
 
 typedef struct {
@@ -150,11 +150,15 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
  * origin), for Vico-Greengard the inverse transform of i k_a times eq. (3) on
  * the 4N grid.  Its transform on the doubled grid is -i times a real octant
  * (sine transform along a), stored by fsp_precompute.  The forward transforms
- * along axes 2 and 1 run once; then for each component the axis-0 pass reads
- * that spectrum and writes the second half of the workspace, and the inverse
- * passes produce the component.  Needs a plan created with FSP_WANT_GRAD
+ * along axes 2 and 1 run once; the axis-0 pass writes every output's
+ * spectrum (components to the workspace's other three spectra, phi in place)
+ * and one launch of each inverse pass takes them all.  The axis-0 pass has
+ * variants of its own: 0 and 1 are one launch for every output (the spectrum
+ * read and transformed once), 2 one launch per output (fewer registers; for
+ * long pencils).  Needs a plan created with FSP_WANT_GRAD
  * (else FSP_ERR_INVALID_ARG); FSP_ERR_NOT_READY before bind + precompute.
- * Uses the plan's schedule with separate passes 1-3.  Asynchronous on
+ * Uses the plan's schedule with separate passes 1-3, the axis-0 variant as
+ * chosen by fsp_autotune, else the schedule's.  Asynchronous on
  * `stream`; allocates nothing. */
 fsp_status fsp_solve_grad(fsp_plan p, const void* rho, void* phi, void* grad, void* stream);
 
@@ -179,8 +183,12 @@ fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants /* [5] */);
  * `stream`.  times_ms (NULL or [5 * 3 + 2]) receives the median time of each
  * variant, times_ms[pass * 3 + variant], then the time of passes 1-3 fused and
  * of passes 1-3 with the best separate variants (0 when fusion is not
- * supported); the fused schedule is kept when it is faster.  If a solve fails
- * its status is returned and the plan keeps a valid (untuned) schedule. */
+ * supported); the fused schedule is kept when it is faster.  On a plan with
+ * FSP_WANT_GRAD it also times the gradient solve's axis-0 pass (four outputs)
+ * in each of its variants and keeps the fastest for fsp_solve_grad
+ * (fsp_plan_set_schedule drops that choice: the gradient then follows the
+ * schedule).  If a solve fails its status is returned and the plan keeps a
+ * valid (untuned) schedule. */
 fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* stream, float* times_ms);
 
 /* count independent solves (each with its own plan, and so its own

@@ -224,9 +224,10 @@ struct fsp_plan_s {
   int chunks = 1;       // column chunks for passes 1-3
   int gather_min = fsp::CONV_GATHER_MIN_BLOCKS;  // axis-0 grid size from which the lone column is gathered
   size_t tw_row_off[fsp::NUM_PLANS]{}, tw_c1_off[fsp::NUM_PLANS]{}, tw_c0_off[fsp::NUM_PLANS]{}, oct_off = 0;
-  bool grad = false;        // FSP_WANT_GRAD: derivative octants and a second workspace
+  bool grad = false;        // FSP_WANT_GRAD: derivative octants and three more spectra
   size_t grad_off[3]{};     // offsets of the derivative octants in the Green's buffer
-  size_t work1_bytes = 0;   // one workspace S (the second, if any, follows it)
+  int grad_p3 = -1;         // axis-0 variant of the gradient solve (-1: from the schedule)
+  size_t work1_bytes = 0;   // one workspace S (the gradient's other spectra follow it)
   int var[5]{};  // schedule variant of each pass
   size_t ghat_bytes = 0, work_bytes = 0, pre_bytes = 0;
   std::vector<char> tw_host;      // image of [0, oct_off) of the Green's buffer
@@ -278,7 +279,7 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::array<int, 5>> g_tuned;
+std::map<TuneKey, std::array<int, 6>> g_tuned;  // schedule, then the gradient's axis-0 variant
 
 double model_bytes(const fsp_plan_s* p) {
   // P1 reads rho, writes (n2+1) n1 n0 complex; P2 reads that, writes 2 n1 (n2+1) n0;
@@ -377,12 +378,14 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     if (const char* e = std::getenv("FSP_CONV_GATHER_MIN")) p->gather_min = std::max(0, std::atoi(e));
   }
   p->work1_bytes = align_up((size_t)p->n[0] * p->plane * cb, 256);
-  p->work_bytes = (p->grad ? 2 : 1) * p->work1_bytes;
+  p->work_bytes = (p->grad ? 4 : 1) * p->work1_bytes;  // the gradient: S and three more spectra
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(TuneKey{p->n[0], p->n[1], p->n[2], d.prec});
-    if (it != g_tuned.end())
+    if (it != g_tuned.end()) {
       for (int i = 0; i < 5; ++i) p->var[i] = it->second[i];
+      p->grad_p3 = it->second[5];
+    }
   }
   // the column kernels address a pencil's rows with 32-bit element offsets
   if ((long long)(2 * p->n[0]) * p->plane >= (1LL << 31)) {
@@ -769,6 +772,39 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
   return solve_one(p, rho, phi, reinterpret_cast<hipStream_t>(stream), first, last);
 }
 
+// The gradient solve of one item: separate passes 1-3, the axis-0 pass in the
+// gradient's own variants (p3; -1 follows the schedule).  The three components
+// go to the workspace's other spectra, phi (when not NULL) in place in S, last;
+// passes 4 and 5 take the outputs as the items of one launch each.
+static fsp::SolveGeom grad_geom(const fsp_plan_s* p, const void* rho, void* phi, void* grad, int p3) {
+  int var[5];
+  for (int i = 0; i < 5; ++i) var[i] = p->var[i];
+  if (var[1] == fsp::FUSED) var[1] = var[2] = var[3] = 0;
+  if (p3 >= 0) var[2] = p3;
+  fsp::SolveGeom g = group_geom(p, var);
+  const int gp = p->d.prec == FSP_F64 ? fsp::grad_cfg<double>(2 * p->n[0], var[2]).pid
+                                      : fsp::grad_cfg<float>(2 * p->n[0], var[2]).pid;
+  g.tw_c0 = static_cast<const char*>(p->ghat_read) + p->tw_c0_off[gp];
+  add_item(g, p, rho, nullptr);
+  const size_t field = (size_t)p->n[0] * p->n[1] * p->n[2] * p->rb;
+  const char* gb = static_cast<const char*>(p->ghat_read);
+  for (int a = 0; a < 3; ++a) {
+    g.ocomp[a] = 1 + a;
+    g.oghat[a] = gb + p->grad_off[a];
+    g.owork[a] = static_cast<char*>(p->work) + (a + 1) * p->work1_bytes;
+    g.ophi[a] = grad ? static_cast<char*>(grad) + a * field : nullptr;
+  }
+  g.nout = 3;
+  if (phi) {
+    g.ocomp[3] = 0;
+    g.oghat[3] = gb + p->oct_off;
+    g.owork[3] = p->work;
+    g.ophi[3] = phi;
+    g.nout = 4;
+  }
+  return g;
+}
+
 fsp_status fsp_solve_grad(fsp_plan p, const void* rho, void* phi, void* grad, void* stream) {
   if (!p || !rho || !grad) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_grad: NULL argument");
   if (!p->grad) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_grad: the plan was created without FSP_WANT_GRAD");
@@ -784,30 +820,7 @@ fsp_status fsp_solve_grad(fsp_plan p, const void* rho, void* phi, void* grad, vo
   if (e != hipSuccess) return fail_hip(e, "fsp_solve_grad: hipSetDevice");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool f64 = p->d.prec == FSP_F64;
-  // separate passes 1-3, and an axis-0 kernel that can write out of place
-  int var[5];
-  for (int i = 0; i < 5; ++i) var[i] = p->var[i];
-  if (var[1] == fsp::FUSED) var[1] = var[2] = var[3] = 0;
-  if (var[2] == 2) var[2] = 0;  // the derivative multiply is instantiated for axis-0 variants 0 and 1
-  fsp::SolveGeom g = group_geom(p, var);
-  add_item(g, p, rho, nullptr);
-  e = run_group(g, f64, 0, 1, s);  // the forward transforms along axes 2 and 1, once
-  const char* gb = static_cast<const char*>(p->ghat_read);
-  void* work2 = static_cast<char*>(p->work) + p->work1_bytes;
-  for (int a = 0; a < 3 && e == hipSuccess; ++a) {  // P3 reads S, writes the second workspace
-    g.comp = 1 + a;
-    g.ghat[0] = gb + p->grad_off[a];
-    g.work_out[0] = work2;
-    g.phi[0] = static_cast<char*>(grad) + a * field;
-    e = run_group(g, f64, 2, 4, s);
-  }
-  if (phi && e == hipSuccess) {  // the potential last: its axis-0 pass works in place on S
-    g.comp = 0;
-    g.ghat[0] = gb + p->oct_off;
-    g.work_out[0] = nullptr;
-    g.phi[0] = phi;
-    e = run_group(g, f64, 2, 4, s);
-  }
+  e = run_group(grad_geom(p, rho, phi, grad, p->grad_p3), f64, 0, 4, s);
   if (e != hipSuccess) return fail_hip(e, "fsp_solve_grad");
   return FSP_OK;
 }
@@ -838,6 +851,7 @@ fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants) {
       return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: variant out of range");
   }
   for (int i = 0; i < 5; ++i) p->var[i] = variants[i];
+  p->grad_p3 = -1;  // the gradient solve follows this schedule
   return FSP_OK;
 }
 
@@ -932,6 +946,29 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
     times_ms[5 * fsp::NUM_VARIANTS] = times_ms[5 * fsp::NUM_VARIANTS + 1] = 0.0f;
   }
   for (int i = 0; i < 5; ++i) p->var[i] = best[i];
+  // the gradient solve's axis-0 pass (four outputs), each of its variants
+  if (e == hipSuccess && p->grad) {
+    const bool f64 = p->d.prec == FSP_F64;
+    float best_ms = 1e30f;
+    int best_v = 0;
+    for (int v = 0; v < fsp::NUM_VARIANTS && e == hipSuccess; ++v) {
+      const fsp::SolveGeom g = grad_geom(p, rho, phi, nullptr, v);
+      float rep_ms[8] = {};
+      for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+        e = run_group(g, f64, 0, 1, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = run_group(g, f64, 2, 2, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (r > 0) rep_ms[r - 1] = ms;
+      }
+      const float ms = median_ms(rep_ms, reps);
+      if (e == hipSuccess && ms < best_ms) best_ms = ms, best_v = v;
+    }
+    if (e == hipSuccess) p->grad_p3 = best_v;
+  }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail_hip(e, "fsp_autotune");
@@ -940,8 +977,10 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
   if (st != FSP_OK) return st;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    std::array<int, 5> a;
+    std::array<int, 6> a;
     for (int i = 0; i < 5; ++i) a[i] = best[i];
+    auto it = g_tuned.find(TuneKey{p->n[0], p->n[1], p->n[2], p->d.prec});
+    a[5] = p->grad ? p->grad_p3 : it != g_tuned.end() ? it->second[5] : -1;
     g_tuned[TuneKey{p->n[0], p->n[1], p->n[2], p->d.prec}] = a;
   }
   return FSP_OK;

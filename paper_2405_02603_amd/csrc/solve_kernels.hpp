@@ -35,6 +35,7 @@ namespace fsp {
 // Up to MAX_ITEMS independent solves of one shape share a launch; blockIdx.y
 // selects the item, whose buffers are passed by value in the kernel arguments.
 constexpr int MAX_ITEMS = 16;
+constexpr int MAX_OUT = 4;  // outputs of the gradient solve's axis-0 pass: three components and phi
 
 struct ColArgs {
   void* data[MAX_ITEMS];      // S of each item
@@ -50,8 +51,11 @@ struct ColArgs {
   long long g_k1_stride;      // P3: reals between Green's blocks k1 (tiles (n0+1) TC)
   int ntail;                  // P3: leading blocks that gather column ncols - 1 over TC k1 pairs
   int gather_min;             // P3 (host side): grid size from which the launcher gathers
-  int comp;                   // P3: 0 potential (real multiply); 1 + a derivative along axis a
-  void* out[MAX_ITEMS];       // P3 derivative: result spectrum of each item (else in place in data)
+  // P3 with several outputs from one item (the gradient solve; nout == 0 otherwise)
+  int nout;                   // outputs (1 .. MAX_OUT)
+  int ocomp[MAX_OUT];         // multiply of output o: 0 potential (real); 1 + a derivative along axis a
+  const void* oghat[MAX_OUT];   // table of output o, blocked as ghat
+  void* oout[MAX_OUT];          // result spectrum of output o (may be data[0]: in place)
 };
 
 struct RowArgs {
@@ -179,13 +183,19 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
 // the table values of their forward butterflies once, for both sets.
 // TWF: the plan's complete twiddle table is read into LDS once per block, so
 // the butterflies load every power instead of multiplying it out of six.
-// GRAD: the multiply of a derivative table (a.comp) and the result written to
-// a.out; a separate instantiation, so the potential's kernel carries none of it.
-template <typename T, int L, int PID, int TC, int NQ, bool TWF = false, bool GRAD = false>
+// NOUT > 0 (the gradient solve): one forward transform per pencil set, then
+// a.nout outputs (NOUT == 1: exactly one): output o multiplies by table
+// a.oghat[o] (a.ocomp[o]: 0 the potential's, 1 + a the derivative along axis
+// a) and goes to a.oout[o] (which may be S itself: the block has read its
+// pencils before it writes).  One item per launch; separate instantiations, so
+// the potential's kernel carries none of it.  With NOUT == 1 the spectrum is
+// not held through a loop (fewer registers).
+template <typename T, int L, int PID, int TC, int NQ, bool TWF = false, int NOUT = 0>
 __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
+  constexpr bool GRAD = NOUT > 0;
   constexpr int K = plan_len(L, PID);
   static_assert(!TWF || K > 1, "single-stage plans have no twiddles");
-  constexpr bool PRE = K == 2 && !TWF && sizeof(T) == 4;  // float64 keeps its registers for occupancy
+  constexpr bool PRE = K == 2 && !TWF && !GRAD && sizeof(T) == 4;  // the others keep their registers for occupancy
   constexpr int NT = TC * NQ;
   constexpr int TWN = TWF ? (twf_size(L, PID) + NT - 1) / NT : 1;  // table entries per thread
   __shared__ cx<T> lds[K > 1 ? L * TC : 1];
@@ -233,41 +243,43 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
 
   // Green's values for the rows this thread holds after the forward transform;
   // the octant is stored in column tiles of TC, so a tile's rows are contiguous.
-  const T* g = reinterpret_cast<const T*>(a.ghat[blockIdx.y]) + (long long)p * a.g_k1_stride +
-               (long long)(col / TC) * (L / 2 + 1) * TC + (col % TC);
-  T gv[Lf::J][Lf::R];
+  // GRAD: the table of output o is a.oghat[o], in the same layout.
+  const long long goff = (long long)p * a.g_k1_stride + (long long)(col / TC) * (L / 2 + 1) * TC + (col % TC);
+  auto load_g = [&](const void* table, T (&gv)[Lf::J][Lf::R]) {
+    const T* g = reinterpret_cast<const T*>(table) + goff;
 #pragma unroll
-  for (int j = 0; j < Lf::J; ++j) {
-    const int b = q + NQ * j;
-    const bool ok = cok && ((Lf::NB % NQ == 0) || b < Lf::NB);
+    for (int j = 0; j < Lf::J; ++j) {
+      const int b = q + NQ * j;
+      const bool ok = cok && ((Lf::NB % NQ == 0) || b < Lf::NB);
 #pragma unroll
-    for (int m = 0; m < Lf::R; ++m) {
-      const int k0 = b + m * Lf::NB;
-      const int kf = k0 <= L / 2 ? k0 : L - k0;
-      gv[j][m] = ok ? g[kf * TC] : T(0);
+      for (int m = 0; m < Lf::R; ++m) {
+        const int k0 = b + m * Lf::NB;
+        const int kf = k0 <= L / 2 ? k0 : L - k0;
+        gv[j][m] = ok ? g[kf * TC] : T(0);
+      }
     }
-  }
+  };
+  T gv[Lf::J][Lf::R];
+  load_g(GRAD ? a.oghat[0] : a.ghat[blockIdx.y], gv);
+  // GRAD with registers to spare: the next output's table values are loaded
+  // while the current output is transformed
+  constexpr bool GPRE = NOUT > 1 && sizeof(T) * L / NQ <= 64;
+  T gn[GPRE ? Lf::J : 1][GPRE ? Lf::R : 1];
 
   // k1 = p and its partner 2 n1 - p share the Green's rows; p = 0 and p = n1
   // have no partner (uniform in a block unless the block is gathered).
   const bool two = cok && !(p == 0 || p == a.n1);
-  cx<T>* base_a = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)p * a.outer_stride + col;
-  cx<T>* base_b = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)(2 * a.n1 - p) * a.outer_stride + col;
-  cx<T>* out_a = base_a;
-  cx<T>* out_b = base_b;
-  if constexpr (GRAD) {
-    cx<T>* obase = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]);
-    out_a = obase + (long long)p * a.outer_stride + col;
-    out_b = obase + (long long)(2 * a.n1 - p) * a.outer_stride + col;
-  }
+  const long long off_a = (long long)p * a.outer_stride + col;
+  const long long off_b = (long long)(2 * a.n1 - p) * a.outer_stride + col;
+  cx<T>* const data = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]);
   // The derivative tables are odd along their axis: their transform is -i T with
   // the real octant T read at the folded frequency and negated on the upper half
   // of that axis (k0 > n0; for axis 1 the partner 2 n1 - p; axis 2 holds k2 <= n2).
-  auto multiply = [&](cx<T>& w, T g, int k0, bool upper_k1) {
-    if constexpr (!GRAD) {
+  auto multiply = [&](cx<T>& w, T g, int comp, int k0, bool upper_k1) {
+    if (!GRAD || comp == 0) {
       w = cscale(w, g);
     } else {
-      const bool neg = a.comp == 1 ? (k0 > L / 2) : (a.comp == 2 && upper_k1);
+      const bool neg = comp == 1 ? (k0 > L / 2) : (comp == 2 && upper_k1);
       const T t = neg ? -g : g;
       w = cx<T>{t * w.y, -t * w.x};  // w * (-i t)
     }
@@ -281,46 +293,34 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? ld_once(&base[(b + r * F::NB) * rs]) : czero<T>();
     }
   };
-  auto run_set = [&](cx<T>* base, const cx<T> (&raw)[F::J][F::R / 2], bool st, bool upper_k1) {
-    cx<T> v[F::J][F::R];
+  const cx<T>* tws = TWF ? static_cast<const cx<T>*>(twl) : tw;
+  // The spectrum of one pencil set (in the layout of the last forward stage)
+  // times one table, back to space, the first half stored at base.
+  auto finish = [&](const cx<T> (&w)[Lf::J][Lf::R], const T (&gt)[Lf::J][Lf::R], int comp, bool upper_k1,
+                    cx<T>* base, bool st) {
+    cx<T> x[Lf::J][Lf::R];
 #pragma unroll
-    for (int j = 0; j < F::J; ++j) {
+    for (int j = 0; j < Lf::J; ++j) {
+      const int b = q + NQ * j;
 #pragma unroll
-      for (int r = 0; r < F::R; ++r) v[j][r] = r < F::R / 2 ? raw[j][r] : czero<T>();
-      Dft<F::R, false, T>::run(v[j]);
+      for (int m = 0; m < Lf::R; ++m) {
+        x[j][m] = w[j][m];
+        multiply(x[j][m], gt[j][m], comp, b + m * Lf::NB, upper_k1);
+      }
+      Dft<Lf::R, true, T>::run(x[j]);  // K == 1: the whole inverse; else its first stage (span 1)
     }
     if constexpr (K == 1) {
 #pragma unroll
-      for (int j = 0; j < F::J; ++j) {
+      for (int j = 0; j < Lf::J; ++j) {
         const int b = q + NQ * j;
-        if (st && ((F::NB % NQ == 0) || b < F::NB)) {
+        if (st && ((Lf::NB % NQ == 0) || b < Lf::NB)) {
 #pragma unroll
-          for (int m = 0; m < F::R; ++m) multiply(v[j][m], gv[j][m], b + m * F::NB, upper_k1);
-          Dft<F::R, true, T>::run(v[j]);
-#pragma unroll
-          for (int m = 0; m < F::R / 2; ++m) put<T, PASS_CONV>(&base[(b + m * F::NB) * rs], v[j][m]);
+          for (int m = 0; m < Lf::R / 2; ++m) put<T, PASS_CONV>(&base[(b + m * Lf::NB) * rs], x[j][m]);
         }
       }
     } else {
-      const cx<T>* tws = TWF ? static_cast<const cx<T>*>(twl) : tw;
-      write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
       lds_barrier();
-      lds_stages<T, L, PID, false, 1, K - 1, NQ, false, TWF>(lds, tws, q, idx);
-      cx<T> w[Lf::J][Lf::R];
-      if constexpr (PRE)
-        lds_last_stage_pre<T, L, PID, false, NQ, false>(lds, tbf, q, idx, w);
-      else
-        lds_last_stage<T, L, PID, false, NQ, false, TWF>(lds, tws, q, idx, w);
-      // multiply, then the first inverse stage (span 1) in registers
-#pragma unroll
-      for (int j = 0; j < Lf::J; ++j) {
-        const int b = q + NQ * j;
-#pragma unroll
-        for (int m = 0; m < Lf::R; ++m) multiply(w[j][m], gv[j][m], b + m * Lf::NB, upper_k1);
-        Dft<Lf::R, true, T>::run(w[j]);
-      }
-      lds_barrier();
-      write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, w, q, idx);
+      write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, x, q, idx);
       lds_barrier();
       lds_stages<T, L, PID, true, 1, K - 1, NQ, true, TWF>(lds, tws, q, idx);
       cx<T> u[Li::J][Li::R];
@@ -335,11 +335,70 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       }
     }
   };
+  // set: 0 for k1 = p, 1 for its partner (whose outputs come last in the block)
+  auto run_set = [&](int set, const cx<T> (&raw)[F::J][F::R / 2], bool st) {
+    const bool upper_k1 = set == 1;
+    const long long off = set == 0 ? off_a : off_b;
+    cx<T> v[F::J][F::R];
+#pragma unroll
+    for (int j = 0; j < F::J; ++j) {
+#pragma unroll
+      for (int r = 0; r < F::R; ++r) v[j][r] = r < F::R / 2 ? raw[j][r] : czero<T>();
+      Dft<F::R, false, T>::run(v[j]);
+    }
+    cx<T> w[Lf::J][Lf::R];
+    if constexpr (K == 1) {
+      static_assert(K > 1 || (F::J == Lf::J && F::R == Lf::R), "a one-stage plan is its own last stage");
+#pragma unroll
+      for (int j = 0; j < Lf::J; ++j)
+#pragma unroll
+        for (int m = 0; m < Lf::R; ++m) w[j][m] = v[j][m];
+    } else {
+      write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+      lds_barrier();
+      lds_stages<T, L, PID, false, 1, K - 1, NQ, false, TWF>(lds, tws, q, idx);
+      if constexpr (PRE)
+        lds_last_stage_pre<T, L, PID, false, NQ, false>(lds, tbf, q, idx, w);
+      else
+        lds_last_stage<T, L, PID, false, NQ, false, TWF>(lds, tws, q, idx, w);
+    }
+    if constexpr (!GRAD) {
+      finish(w, gv, 0, upper_k1, data + off, st);
+    } else {
+      // every output from the one forward transform; the table values of
+      // output 0 are in gv on entry (loaded at the start, or prefetched by the
+      // other set's last output)
+      // (one output: gv serves both sets)
+      const int nout = NOUT == 1 ? 1 : a.nout;
+#pragma unroll 1
+      for (int o = 0; o < nout; ++o) {
+        const bool last = set == 1 || !(gathered || two);  // no set follows this one
+        if constexpr (GPRE) {
+          if (o + 1 < nout) load_g(a.oghat[o + 1], gn);
+          else if (!last && nout > 1) load_g(a.oghat[0], gn);
+        } else if ((o > 0 || set == 1) && nout > 1) {
+          load_g(a.oghat[o], gv);
+        }
+        finish(w, gv, a.ocomp[o], upper_k1, reinterpret_cast<cx<T>*>(a.oout[o]) + off, st);
+        if constexpr (GPRE) {
+          if (nout > 1) {
+#pragma unroll
+            for (int j = 0; j < Lf::J; ++j)
+#pragma unroll
+              for (int m = 0; m < Lf::R; ++m) gv[j][m] = gn[j][m];
+          }
+        }
+      }
+    }
+  };
+  // GRAD where registers are short (long pencils per thread): the second set
+  // is read after the first set's outputs, not held through them
+  constexpr bool LATE_B = NOUT > 1 && sizeof(T) * L / NQ >= 128;
   cx<T> raw_a[F::J][F::R / 2], raw_b[F::J][F::R / 2];
   issue_fence();
-  load_set(base_a, true, raw_a);
+  load_set(data + off_a, true, raw_a);
   issue_fence();
-  load_set(base_b, two, raw_b);
+  if constexpr (!LATE_B) load_set(data + off_b, two, raw_b);
   issue_fence();
   if constexpr (TWF) {  // the table arrived before the pencils; visible after the first barrier
 #pragma unroll
@@ -348,10 +407,11 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       if (e < twf_size(L, PID)) twl[e] = twr[i];
     }
   }
-  run_set(out_a, raw_a, cok, false);
+  run_set(0, raw_a, cok);
   if (gathered || two) {  // block-uniform: barriers inside
+    if constexpr (LATE_B) load_set(data + off_b, two, raw_b);
     lds_barrier();
-    run_set(out_b, raw_b, two, true);
+    run_set(1, raw_b, two);
   }
 }
 

@@ -158,6 +158,23 @@ hipError_t launch_p5(int LC, int v, const RowArgs& a, int items, hipStream_t s) 
   return hipGetLastError();
 }
 
+// Axis-0 pass of the gradient solve.  Variants 0 and 1: one launch writes
+// every output from one forward transform, the spectrum held in registers
+// through the outputs; for pencils of 256 and more variant 0 spreads a pencil
+// over more threads, with plan 1: up to 1024 threads a block through 512
+// (radix-8 stages), 512 threads beyond (a 1024-thread block is held to 128
+// registers a thread); variant 1 is the column pass's variant 1.  Variant 2:
+// one launch per output in the column pass's variant-0 shape (each reads the
+// spectrum again, with fewer registers).  The tile stays col_tc (the layout
+// of the tables).
+template <typename T>
+__host__ __device__ constexpr TileCfg grad_cfg(int L, int v) {
+  const int tc = col_tc<T>(L);
+  if (v == 0 && L >= 256 && L <= 512) return {1, tc, 1024 / tc < L / 8 ? 1024 / tc : L / 8};
+  if (v == 0 && L > 512) return {1, tc, 512 / tc};
+  return col_cfg<T>(L, v == 2 ? 0 : v);
+}
+
 template <typename T>
 int col_tiles(int L) {
   return col_tc<T>(L);
@@ -193,16 +210,18 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
     const dim3 grid((unsigned)(a.nouter * a.ntiles), (unsigned)items);                              \
     const dim3 block(c.tiles * c.nq);                                                               \
     if (kind == 2) {                                                                                \
-      if (a.comp != 0) {                                                                            \
-        /* a derivative table: variants 0 and 1 have an instantiation for it */                    \
-        if constexpr (VV < 2) {                                                                     \
-          const ColArgs b = conv_gather(a, c.tiles);                                                \
-          hipLaunchKernelGGL((k_col_conv<T, LV, c.pid, c.tiles, c.nq, false, true>),                \
-                             dim3((unsigned)(b.nouter * b.ntiles + b.ntail), (unsigned)items),      \
-                             block, 0, s, b);                                                       \
-        } else {                                                                                    \
-          return hipErrorInvalidValue;                                                              \
-        }                                                                                           \
+      if (a.nout > 0) {                                                                             \
+        /* the gradient solve: variants 0 and 1 all outputs, variant 2 exactly one */              \
+        constexpr TileCfg gc = grad_cfg<T>(LV, VV);                                                 \
+        if (items != 1 || a.nout > MAX_OUT || (VV == 2 && a.nout != 1)) return hipErrorInvalidValue; \
+        const ColArgs b = conv_gather(a, gc.tiles);                                                 \
+        const dim3 gridg((unsigned)(b.nouter * b.ntiles + b.ntail), 1u);                            \
+        if constexpr (VV < 2)                                                                       \
+          hipLaunchKernelGGL((k_col_conv<T, LV, gc.pid, gc.tiles, gc.nq, false, MAX_OUT>), gridg,   \
+                             dim3(gc.tiles * gc.nq), 0, s, b);                                      \
+        else                                                                                        \
+          hipLaunchKernelGGL((k_col_conv<T, LV, gc.pid, gc.tiles, gc.nq, false, 1>), gridg,         \
+                             dim3(gc.tiles * gc.nq), 0, s, b);                                      \
       } else if constexpr (conv_pipelined<T>(LV, VV)) {                                             \
         ColArgs b = a;                                                                              \
         b.ntail = 0;                                                                                \
@@ -302,8 +321,14 @@ struct SolveGeom {
   void* work[MAX_ITEMS];        // S of each item
   const void* rho[MAX_ITEMS];
   void* phi[MAX_ITEMS];
-  int comp;                     // P3 multiply: 0 potential, 1 + a derivative along axis a
-  void* work_out[MAX_ITEMS];    // derivatives: P3 result and P4/P5 workspace (potential: NULL, in place)
+  // Gradient solve (one item; nout == 0 otherwise): the axis-0 pass reads S of
+  // item 0 (once, or once per output with variant 2) and writes nout spectra,
+  // which passes 4 and 5 take as items.  An output in place in S comes last.
+  int nout;
+  int ocomp[MAX_OUT];           // 0 potential, 1 + a derivative along axis a
+  const void* oghat[MAX_OUT];   // table of each output
+  void* owork[MAX_OUT];         // spectrum of each output (S itself for at most one)
+  void* ophi[MAX_OUT];          // result of each output
 };
 
 // Passes first..last of one solve (0 = P1 ... 4 = P5).
@@ -330,11 +355,17 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
   for (int i = 0; i < g.items; ++i) {
     cc.data[i] = g.work[i];
     cc.ghat[i] = g.ghat[i];
-    cc.out[i] = g.work_out[i];
   }
-  cc.comp = g.comp;
-  // P4 and P5 work on the P3 result
-  void* const* after = g.work_out[0] ? g.work_out : g.work;
+  cc.nout = g.nout;
+  for (int o = 0; o < g.nout; ++o) {
+    cc.ocomp[o] = g.ocomp[o];
+    cc.oghat[o] = g.oghat[o];
+    cc.oout[o] = g.owork[o];
+  }
+  // P4 and P5 work on the P3 results
+  void* const* after = g.nout ? g.owork : g.work;
+  void* const* result = g.nout ? g.ophi : g.phi;
+  const int npost = g.nout ? g.nout : g.items;
   cc.ncols = g.n2 + 1;
   cc.row_stride = plane;
   cc.outer_stride = P;
@@ -367,27 +398,41 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
         set_cols(ca, tc2, c0, c1);
         ca.tw = g.tw_c1[1];
         return launch_col<T>(2 * g.n1, g.var[1], 0, ca, g.items, s);
-      case 2: set_cols(cc, tc0, c0, c1); return launch_col<T>(2 * g.n0, g.var[2], 2, cc, g.items, s);
+      case 2:
+        set_cols(cc, tc0, c0, c1);
+        if (g.nout && g.var[2] == 2) {  // one launch per output, in order (an in-place one is last)
+          hipError_t r = hipSuccess;
+          for (int o = 0; o < g.nout && r == hipSuccess; ++o) {
+            ColArgs c3 = cc;
+            c3.nout = 1;
+            c3.ocomp[0] = g.ocomp[o];
+            c3.oghat[0] = g.oghat[o];
+            c3.oout[0] = g.owork[o];
+            r = launch_col<T>(2 * g.n0, 2, 2, c3, 1, s);
+          }
+          return r;
+        }
+        return launch_col<T>(2 * g.n0, g.var[2], 2, cc, g.items, s);
       case 3: {
         ColArgs c4 = ca;
-        for (int i = 0; i < g.items; ++i) c4.data[i] = after[i];
+        for (int i = 0; i < npost; ++i) c4.data[i] = after[i];
         set_cols(c4, tc4, c0, c1);
         c4.tw = g.tw_c1[3];
-        return launch_col<T>(2 * g.n1, g.var[3], 1, c4, g.items, s);
+        return launch_col<T>(2 * g.n1, g.var[3], 1, c4, npost, s);
       }
       case 4:
-        for (int i = 0; i < g.items; ++i) {
+        for (int i = 0; i < npost; ++i) {
           ra.in[i] = after[i];
-          ra.out[i] = g.phi[i];
+          ra.out[i] = result[i];
         }
         ra.tw = g.tw_row[4];
-        return launch_p5<T>(g.n2, g.var[4], ra, g.items, s);
+        return launch_p5<T>(g.n2, g.var[4], ra, npost, s);
       default: return hipErrorInvalidValue;
     }
   };
   hipError_t e = hipSuccess;
-  if (g.var[1] == FUSED && g.comp != 0) return hipErrorInvalidValue;  // the caller picks separate passes
-  if (g.comp != 0 && !g.work_out[0]) return hipErrorInvalidValue;     // derivatives are written out of place
+  if (g.nout < 0 || g.nout > MAX_OUT || (g.nout && (g.items != 1 || g.var[1] == FUSED)))
+    return hipErrorInvalidValue;  // one item, separate passes: the caller picks them
   if (g.var[1] == FUSED) {
     // passes 1-3 as one fused kernel over column tiles: a range holds all of
     // them or none (pass 0 or pass 4 alone)

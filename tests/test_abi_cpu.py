@@ -179,14 +179,14 @@ def test_gradient_plan_sizes_offsets_and_errors(lib):
     assert lib.fsp_plan_octant_offset(h0, 1, ctypes.byref(off)) == _lib.FSP_ERR_INVALID_ARG
     dummy = ctypes.c_void_p(256)
     assert lib.fsp_solve_grad(h0, dummy, None, dummy, None) == _lib.FSP_ERR_INVALID_ARG
-    # with it: three more octants in the Green's buffer and a second spectrum in the workspace
+    # with it: three more octants in the Green's buffer and three more spectra in the workspace
     d = _desc(n=(16, 24, 32))
     d.flags = _lib.FSP_WANT_GRAD
     st, h = _create(lib, d)
     assert st == _lib.FSP_OK
     g, w = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.fsp_plan_bytes(h, ctypes.byref(g), ctypes.byref(w)) == _lib.FSP_OK
-    assert w.value == 2 * w0.value
+    assert w.value == 4 * w0.value
     layout_off = ctypes.c_size_t()
     assert lib.fsp_plan_ghat_layout(h, ctypes.byref(layout_off), None) == _lib.FSP_OK
     offs = []

@@ -165,3 +165,27 @@ def test_gradient_full_size_256(torch_cuda, kind):
         plan.close()
         del r, grad
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_gradient_long_axis0_pencils_every_variant(torch_cuda, prec, tol):
+    """Axis-0 pencils of 256 to 1024 points (the gradient's own tile shapes, several tiles and a
+    ragged last column along axis 2), every variant of that pass, against the oracle."""
+    torch = torch_cuda
+    dt = torch.float64 if prec == "f64" else torch.float32
+    lo, hi = (-1.0, -0.5, -0.75), (1.0, 0.5, 0.75)
+    for n in [(128, 12, 24), (256, 8, 48), (384, 8, 12), (512, 8, 24)]:
+        rho = W.random_field(n, 17)
+        refs = _grad_ref(rho, "vico_dct", lo, hi)
+        phi_ref = reference(rho, "vico_dct", lo, hi, use_direct=False)
+        plan = _plan(n, lo, hi, "vico_dct", prec)
+        r = to_dev(rho, dt)
+        for v in (0, 1, 2):
+            plan.schedule = [0, 0, v, 0, 0]
+            grad, phi = plan.solve_grad(r, want_phi=True)
+            torch.cuda.synchronize()
+            g = to_host(grad)
+            errs = [rel_l2(g[a], refs[a]) for a in range(3)]
+            assert max(errs) <= tol, (n, v, errs)
+            assert rel_l2(to_host(phi), phi_ref) <= tol, (n, v)
+        plan.close()
