@@ -660,13 +660,17 @@ static fsp::SolveGeom group_geom(const fsp_plan_s* p, const int* var) {
   g.gather_min = p->gather_min;
   const char* gb = static_cast<const char*>(p->ghat_read);
   for (int i = 0; i < 5; ++i) g.var[i] = var[i];
-  const int pr1 = fsp::row_cfg<float>(p->n[2], var[0]).pid, pr5 = fsp::row_cfg<float>(p->n[2], var[4]).pid;
+  // the radix plan of a variant may differ between the precisions
+  const bool f64 = p->d.prec == FSP_F64;
+  const int pr1 = f64 ? fsp::row_cfg<double>(p->n[2], var[0]).pid : fsp::row_cfg<float>(p->n[2], var[0]).pid;
+  const int pr5 = f64 ? fsp::row_cfg<double>(p->n[2], var[4]).pid : fsp::row_cfg<float>(p->n[2], var[4]).pid;
   const bool fused = var[1] == fsp::FUSED;
-  const int pc2 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], var[1]).pid;
-  const int pc4 = fused ? 0 : fsp::col_cfg<float>(2 * p->n[1], var[3]).pid;
-  const int pc3 = fused                     ? 0
-                  : p->d.prec == FSP_F64 ? fsp::conv_cfg<double>(2 * p->n[0], var[2]).pid
-                                              : fsp::conv_cfg<float>(2 * p->n[0], var[2]).pid;
+  auto col_pid = [&](int L, int v) { return f64 ? fsp::col_cfg<double>(L, v).pid : fsp::col_cfg<float>(L, v).pid; };
+  const int pc2 = fused ? 0 : col_pid(2 * p->n[1], var[1]);
+  const int pc4 = fused ? 0 : col_pid(2 * p->n[1], var[3]);
+  const int pc3 = fused ? 0
+                  : f64 ? fsp::conv_cfg<double>(2 * p->n[0], var[2]).pid
+                        : fsp::conv_cfg<float>(2 * p->n[0], var[2]).pid;
   for (int i = 0; i < 5; ++i) g.tw_row[i] = g.tw_c1[i] = nullptr;
   g.tw_row[0] = gb + p->tw_row_off[pr1];
   g.tw_row[4] = gb + p->tw_row_off[pr5];

@@ -745,65 +745,85 @@ __global__ __launch_bounds__(NT) void k_slab_conv(SlabArgs a) {
 // Row of n2 = LC reals x (zero-padded to 2 LC): z[n] = x[2n] + i x[2n+1]
 // (n < LC/2, zero above), Z = DFT_LC(z), then for k in [0, LC]
 //   X[k] = (Z[k] + conj Z[LC-k]) / 2 - i e^{-i pi k / LC} (Z[k] - conj Z[LC-k]) / 2.
-template <typename T, int LC, int PID, int TR, int NQ>
+// A block transforms G groups of TR rows, one after the other, and requests
+// every group's input first: a thread keeps G times the bytes in flight.
+template <typename T, int LC, int PID, int TR, int NQ, int G = 1>
 __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
   constexpr int K = plan_len(LC, PID);
   constexpr int LP = row_pitch(LC);
   __shared__ cx<T> lds[TR * LP];
   const int tid = threadIdx.x;
   const int q = tid % NQ, c = tid / NQ;
-  const int row = blockIdx.x * TR + c;
-  const bool rok = row < a.nrows;
-  const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in[blockIdx.y]) + (long long)row * (LC / 2);
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   auto idx = [c](int e) { return c * LP + row_slot(e); };
   using F = FirstStage<LC, PID, false, NQ>;
   static_assert(F::R % 2 == 0, "forward plans start with an even radix");
-
-  cx<T> v[F::J][F::R];
+  // every group's input is requested before the first group is transformed
+  cx<T> raw[G][F::J][F::R / 2];
 #pragma unroll
-  for (int j = 0; j < F::J; ++j) {
-    const int b = q + NQ * j;
-    const bool ok = rok && ((F::NB % NQ == 0) || b < F::NB);
+  for (int g = 0; g < G; ++g) {
+    const int row = ((int)blockIdx.x * G + g) * TR + c;
+    const bool rok = row < a.nrows;
+    const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in[blockIdx.y]) + (long long)row * (LC / 2);
+    issue_fence();
 #pragma unroll
-    for (int r = 0; r < F::R; ++r) v[j][r] = (ok && r < F::R / 2) ? ld_once(&in[b + r * F::NB]) : czero<T>();
-    Dft<F::R, false, T>::run(v[j]);
-  }
-  if constexpr (K == 1) {
-    write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
-  } else {
-    write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
-    lds_barrier();
-    lds_stages<T, LC, PID, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
-    using Ls = LastStage<LC, PID, false, NQ>;
-    cx<T> w[Ls::J][Ls::R];
-    lds_last_stage<T, LC, PID, false, NQ, false>(lds, tw, q, idx, w);
-    lds_barrier();
-#pragma unroll
-    for (int j = 0; j < Ls::J; ++j) {
+    for (int j = 0; j < F::J; ++j) {
       const int b = q + NQ * j;
-      if ((Ls::NB % NQ == 0) || b < Ls::NB) {
+      const bool ok = rok && ((F::NB % NQ == 0) || b < F::NB);
 #pragma unroll
-        for (int m = 0; m < Ls::R; ++m) lds[idx(b + m * Ls::NB)] = w[j][m];
-      }
+      for (int r = 0; r < F::R / 2; ++r) raw[g][j][r] = ok ? ld_once(&in[b + r * F::NB]) : czero<T>();
     }
   }
-  lds_barrier();
-  if (!rok) return;
+  issue_fence();
   const cx<T>* pp = tw + tw_size(LC, PID);
-  const int i0 = row / a.n1, i1 = row - i0 * a.n1;
-  cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
-  constexpr int JO = (LC + 1 + NQ - 1) / NQ;
 #pragma unroll
-  for (int j = 0; j < JO; ++j) {
-    const int k = q + NQ * j;
-    if (k <= LC) {
-      const cx<T> A = lds[idx(k == LC ? 0 : k)];
-      const cx<T> B = conjg(lds[idx(k == 0 ? 0 : LC - k)]);
-      const cx<T> E = {T(0.5) * (A.x + B.x), T(0.5) * (A.y + B.y)};
-      const cx<T> D = {T(0.5) * (A.x - B.x), T(0.5) * (A.y - B.y)};
-      const cx<T> U = cmul(pp[k], D);
-      put<T, PASS_ROW_FWD>(&out[k], cx<T>{E.x + U.y, E.y - U.x});
+  for (int g = 0; g < G; ++g) {
+    const int row = ((int)blockIdx.x * G + g) * TR + c;
+    const bool rok = row < a.nrows;
+    if (g > 0) lds_barrier();
+    cx<T> v[F::J][F::R];
+#pragma unroll
+    for (int j = 0; j < F::J; ++j) {
+#pragma unroll
+      for (int r = 0; r < F::R; ++r) v[j][r] = r < F::R / 2 ? raw[g][j][r] : czero<T>();
+      Dft<F::R, false, T>::run(v[j]);
+    }
+    if constexpr (K == 1) {
+      write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+    } else {
+      write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+      lds_barrier();
+      lds_stages<T, LC, PID, false, 1, K - 1, NQ, false>(lds, tw, q, idx);
+      using Ls = LastStage<LC, PID, false, NQ>;
+      cx<T> w[Ls::J][Ls::R];
+      lds_last_stage<T, LC, PID, false, NQ, false>(lds, tw, q, idx, w);
+      lds_barrier();
+#pragma unroll
+      for (int j = 0; j < Ls::J; ++j) {
+        const int b = q + NQ * j;
+        if ((Ls::NB % NQ == 0) || b < Ls::NB) {
+#pragma unroll
+          for (int m = 0; m < Ls::R; ++m) lds[idx(b + m * Ls::NB)] = w[j][m];
+        }
+      }
+    }
+    lds_barrier();
+    if (rok) {
+      const int i0 = row / a.n1, i1 = row - i0 * a.n1;
+      cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
+      constexpr int JO = (LC + 1 + NQ - 1) / NQ;
+#pragma unroll
+      for (int j = 0; j < JO; ++j) {
+        const int k = q + NQ * j;
+        if (k <= LC) {
+          const cx<T> A = lds[idx(k == LC ? 0 : k)];
+          const cx<T> B = conjg(lds[idx(k == 0 ? 0 : LC - k)]);
+          const cx<T> E = {T(0.5) * (A.x + B.x), T(0.5) * (A.y + B.y)};
+          const cx<T> D = {T(0.5) * (A.x - B.x), T(0.5) * (A.y - B.y)};
+          const cx<T> U = cmul(pp[k], D);
+          put<T, PASS_ROW_FWD>(&out[k], cx<T>{E.x + U.y, E.y - U.x});
+        }
+      }
     }
   }
 }
@@ -812,77 +832,93 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
 // From X[k], k in [0, LC] (half spectrum of a real row of length 2 LC):
 //   Y[n] = (X[n] + conj X[LC-n]) + i e^{+i pi n / LC} (X[n] - conj X[LC-n]),
 //   z = inverse DFT_LC(Y), x[2n] = Re z[n], x[2n+1] = Im z[n]; keep n < LC/2.
-template <typename T, int LC, int PID, int TR, int NQ>
+// G groups of TR rows per block, every group's input requested first, as in P1.
+template <typename T, int LC, int PID, int TR, int NQ, int G = 1>
 __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
   constexpr int K = plan_len(LC, PID);
   constexpr int LP = row_pitch(LC);
   __shared__ cx<T> lds[TR * LP];
   const int tid = threadIdx.x;
   const int q = tid % NQ, c = tid / NQ;
-  const int row = blockIdx.x * TR + c;
-  const bool rok = row < a.nrows;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   auto idx = [c](int e) { return c * LP + row_slot(e); };
-  {
+  constexpr int JI = (LC + 1 + NQ - 1) / NQ;
+  cx<T> raw[G][JI];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int row = ((int)blockIdx.x * G + g) * TR + c;
+    const bool rok = row < a.nrows;
     const int i0 = row / a.n1, i1 = row - i0 * a.n1;
     const cx<T>* in =
         reinterpret_cast<const cx<T>*>(a.in[blockIdx.y]) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
-    constexpr int JI = (LC + 1 + NQ - 1) / NQ;
+    issue_fence();
 #pragma unroll
     for (int j = 0; j < JI; ++j) {
       const int k = q + NQ * j;
-      if (k <= LC) lds[idx(k)] = rok ? ld_once(&in[k]) : czero<T>();
+      raw[g][j] = (rok && k <= LC) ? ld_once(&in[k]) : czero<T>();
     }
   }
-  lds_barrier();
+  issue_fence();
   const cx<T>* pp = tw + tw_size(LC, PID);
   using F = FirstStage<LC, PID, true, NQ>;
-  cx<T> v[F::J][F::R];
 #pragma unroll
-  for (int j = 0; j < F::J; ++j) {
-    const int b = q + NQ * j;
-    if ((F::NB % NQ == 0) || b < F::NB) {
+  for (int g = 0; g < G; ++g) {
+    const int row = ((int)blockIdx.x * G + g) * TR + c;
+    const bool rok = row < a.nrows;
+    if (g > 0) lds_barrier();
 #pragma unroll
-      for (int r = 0; r < F::R; ++r) {
-        const int n = b + r * F::NB;
-        const cx<T> X1 = lds[idx(n)];
-        const cx<T> X2 = conjg(lds[idx(LC - n)]);
-        const cx<T> A = cadd(X1, X2);
-        const cx<T> B = cmulc(csub(X1, X2), pp[n]);
-        v[j][r] = {A.x - B.y, A.y + B.x};
-      }
-      Dft<F::R, true, T>::run(v[j]);
+    for (int j = 0; j < JI; ++j) {
+      const int k = q + NQ * j;
+      if (k <= LC) lds[idx(k)] = raw[g][j];
     }
-  }
-  cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)row * (LC / 2);
-  if constexpr (K == 1) {
-    static_assert(F::R % 2 == 0, "inverse plans end with an even radix");
-    if (rok) {
+    lds_barrier();
+    cx<T> v[F::J][F::R];
 #pragma unroll
-      for (int j = 0; j < F::J; ++j) {
-        const int b = q + NQ * j;
-        if ((F::NB % NQ == 0) || b < F::NB) {
+    for (int j = 0; j < F::J; ++j) {
+      const int b = q + NQ * j;
+      if ((F::NB % NQ == 0) || b < F::NB) {
 #pragma unroll
-          for (int m = 0; m < F::R / 2; ++m) put<T, PASS_ROW_INV>(&out[b + m * F::NB], v[j][m]);
+        for (int r = 0; r < F::R; ++r) {
+          const int n = b + r * F::NB;
+          const cx<T> X1 = lds[idx(n)];
+          const cx<T> X2 = conjg(lds[idx(LC - n)]);
+          const cx<T> A = cadd(X1, X2);
+          const cx<T> B = cmulc(csub(X1, X2), pp[n]);
+          v[j][r] = {A.x - B.y, A.y + B.x};
+        }
+        Dft<F::R, true, T>::run(v[j]);
+      }
+    }
+    cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)row * (LC / 2);
+    if constexpr (K == 1) {
+      static_assert(F::R % 2 == 0, "inverse plans end with an even radix");
+      if (rok) {
+#pragma unroll
+        for (int j = 0; j < F::J; ++j) {
+          const int b = q + NQ * j;
+          if ((F::NB % NQ == 0) || b < F::NB) {
+#pragma unroll
+            for (int m = 0; m < F::R / 2; ++m) put<T, PASS_ROW_INV>(&out[b + m * F::NB], v[j][m]);
+          }
         }
       }
-    }
-  } else {
-    lds_barrier();
-    write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
-    lds_barrier();
-    lds_stages<T, LC, PID, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
-    using Li = LastStage<LC, PID, true, NQ>;
-    static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
-    cx<T> u[Li::J][Li::R];
-    lds_last_stage<T, LC, PID, true, NQ, true>(lds, tw, q, idx, u);
-    if (rok) {
+    } else {
+      lds_barrier();
+      write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
+      lds_barrier();
+      lds_stages<T, LC, PID, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
+      using Li = LastStage<LC, PID, true, NQ>;
+      static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
+      cx<T> u[Li::J][Li::R];
+      lds_last_stage<T, LC, PID, true, NQ, true>(lds, tw, q, idx, u);
+      if (rok) {
 #pragma unroll
-      for (int j = 0; j < Li::J; ++j) {
-        const int b = q + NQ * j;
-        if ((Li::NB % NQ == 0) || b < Li::NB) {
+        for (int j = 0; j < Li::J; ++j) {
+          const int b = q + NQ * j;
+          if ((Li::NB % NQ == 0) || b < Li::NB) {
 #pragma unroll
-          for (int m = 0; m < Li::R / 2; ++m) put<T, PASS_ROW_INV>(&out[b + m * Li::NB], u[j][m]);
+            for (int m = 0; m < Li::R / 2; ++m) put<T, PASS_ROW_INV>(&out[b + m * Li::NB], u[j][m]);
+          }
         }
       }
     }

@@ -10,6 +10,7 @@ struct TileCfg {
   int pid;    // radix plan (fft_core.hpp)
   int tiles;  // TC (column passes: columns per block) or TR (row passes: rows per block)
   int nq;     // threads per pencil
+  int groups = 1;  // row passes: groups of `tiles` rows per block, transformed in turn
 };
 
 // Schedule variants per pencil length; variant 0 is the default and the
@@ -73,7 +74,10 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
     case 96: return v == 0 ? TileCfg{0, 32, 4} : v == 1 ? TileCfg{1, 32, 2} : TileCfg{0, 16, 8};
     case 128: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 8} : TileCfg{0, 32, 8};
     case 192: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 4} : TileCfg{0, 8, 16};
-    case 256: return v == 0 ? TileCfg{0, d ? 8 : 16, 16} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{0, d ? 4 : 8, 16};
+    // 256 in float32: small blocks of 4 rows, 2-4 groups each (more bytes in flight a thread)
+    case 256:
+      return d ? (v == 0 ? TileCfg{0, 8, 16} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{1, 4, 32, 2})
+               : (v == 0 ? TileCfg{0, 4, 16, 4} : v == 1 ? TileCfg{1, 4, 32, 2} : TileCfg{0, 4, 16, 2});
     case 384: return v == 0 ? TileCfg{0, d ? 4 : 8, 8} : v == 1 ? TileCfg{1, 8, 8} : TileCfg{0, 4, 16};
     // 512: the three-stage plan; 64 threads per row over 4 rows keeps 8 waves per SIMD
     case 512: return v == 0 ? TileCfg{1, 4, 64} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{1, 16, 32};
@@ -128,8 +132,9 @@ hipError_t launch_p1(int LC, int v, const RowArgs& a, int items, hipStream_t s) 
 #define FSP_CASE_V(LV, VV)                                                                          \
   if (LC == LV && v == VV) {                                                                        \
     constexpr TileCfg c = row_cfg<T>(LV, VV);                                                       \
-    const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                           \
-    hipLaunchKernelGGL((k_row_r2c<T, LV, c.pid, c.tiles, c.nq>), dim3(blocks, items), dim3(c.tiles * c.nq), 0, s, a); \
+    const int blocks = (a.nrows + c.tiles * c.groups - 1) / (c.tiles * c.groups);                   \
+    hipLaunchKernelGGL((k_row_r2c<T, LV, c.pid, c.tiles, c.nq, c.groups>), dim3(blocks, items),      \
+                       dim3(c.tiles * c.nq), 0, s, a);                                              \
     found = true;                                                                                   \
   }
 #define FSP_CASE(LV) FSP_VARIANTS(FSP_CASE_V, LV)
@@ -146,8 +151,9 @@ hipError_t launch_p5(int LC, int v, const RowArgs& a, int items, hipStream_t s) 
 #define FSP_CASE_V(LV, VV)                                                                          \
   if (LC == LV && v == VV) {                                                                        \
     constexpr TileCfg c = row_cfg<T>(LV, VV);                                                       \
-    const int blocks = (a.nrows + c.tiles - 1) / c.tiles;                                           \
-    hipLaunchKernelGGL((k_row_c2r<T, LV, c.pid, c.tiles, c.nq>), dim3(blocks, items), dim3(c.tiles * c.nq), 0, s, a); \
+    const int blocks = (a.nrows + c.tiles * c.groups - 1) / (c.tiles * c.groups);                   \
+    hipLaunchKernelGGL((k_row_c2r<T, LV, c.pid, c.tiles, c.nq, c.groups>), dim3(blocks, items),      \
+                       dim3(c.tiles * c.nq), 0, s, a);                                              \
     found = true;                                                                                   \
   }
 #define FSP_CASE(LV) FSP_VARIANTS(FSP_CASE_V, LV)
