@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--greens vico_dct]
                     [--no-cpu-baseline] [--cpu-seconds 20] [--skip-f64] [--skip-extras]
-                    [--workload single|batch|serve]
+                    [--workload single|batch|serve|shard]
 
 A step is one full solve (all five passes: axis-2 real transform with the zero
 padding fused, axis-1 forward, axis-0 forward + Green's multiply + inverse,
@@ -110,9 +110,10 @@ def parse(argv=None):
     ap.add_argument("--skip-f64", action="store_true")
     ap.add_argument("--skip-extras", action="store_true", help="skip the gradient and precompute timings")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve", "shard"],
                     help="single: the 256^3 headline; batch: 64 uneven right-hand sides per graph launch; "
-                         "serve: Poisson-arrival serving loop")
+                         "serve: Poisson-arrival serving loop; shard: one GPU's share of an 8-way "
+                         "slab-decomposed solve, at its real shapes")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -437,6 +438,63 @@ def bench_serve(args):
     return 0
 
 
+def bench_shard(args):
+    """One GPU's share of a 256^3 solve slab-decomposed over G = 8 GPUs, at the
+    share's real shapes: P1, P2, P4 and P5 on an n0 / G slab (a (n/G, n, n)
+    plan), P3 on about (n2 + 1) / G of the axis-2 frequencies (a (n, n, n/G)
+    plan: 2 n1 (n/G + 1) pencils of 2 n0 points).  The two all-to-all exchanges
+    between them are not run (one GPU); their ideal time over xGMI is given
+    from the bytes that leave each GPU, as a model."""
+    import torch
+
+    import workloads as W
+    from paper_2405_02603_amd import Plan
+
+    n, G = args.n, 8
+    lo, hi = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+    out = {}
+    for prec in (["f32"] if args.skip_f64 else ["f32", "f64"]):
+        dt = torch.float32 if prec == "f32" else torch.float64
+        rb = 4 if prec == "f32" else 8
+        ms = {}
+        for name, shape, keep in (("slab", (n // G, n, n), (0, 1, 3, 4)), ("columns", (n, n, n // G), (2,))):
+            plan = Plan(n=shape, lo=lo, hi=hi, greens=args.greens, prec=prec)
+            rho = torch.from_numpy(W.random_field(shape, 7)).to(device="cuda", dtype=dt)
+            phi = torch.empty_like(rho)
+            if not args.no_autotune:
+                plan.autotune(rho, phi, reps=4)
+            for _ in range(args.warmup):
+                plan.solve(rho, phi)
+            pm = time_passes(torch, plan, rho, phi, args.steps)
+            pb = pass_bytes(shape, rb)
+            for i in keep:
+                ms[PASS_NAMES[i]] = {"ms": round(pm[i], 5), "bytes": pb[i], "shape": list(shape),
+                                     "GBs": round(pb[i] / (pm[i] * 1e-3) / 1e9, 1)}
+            del plan, rho, phi
+            torch.cuda.empty_cache()
+        total = sum(v["ms"] for v in ms.values())
+        nbytes = sum(v["bytes"] for v in ms.values())
+        # each exchange: this GPU's share of the half spectrum, (G - 1) / G of it leaving, one xGMI link per peer
+        half2 = n * 2 * n * (n + 1) * 2 * rb
+        per_peer = half2 / G / G
+        xgmi = 153e9
+        out[prec] = {"kernel_ms": round(total, 5), "passes": ms, "model_bytes": nbytes,
+                     "hbm_frac_model": round(nbytes / (total * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                     "exchange_model": {"per_peer_bytes": int(per_peer), "links": G - 1, "link_GBs": 153.0,
+                                        "ms_each": round(per_peer / xgmi * 1e3, 5), "count": 2}}
+    r32 = out["f32"]
+    line = {"metric": f"one GPU's share of a {n}^3 solve slab-decomposed over {G} GPUs (pass kernels at the share shapes)",
+            "value": r32["kernel_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": r32["kernel_ms"], "higher_is_better": False, "scaling": "strong", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{args.greens} {n}^3 on [-1,1]^3 split over {G} GPUs: P1/P2/P4/P5 on a "
+                                   f"({n // G},{n},{n}) slab, P3 on a ({n},{n},{n // G}) column share; random field "
+                                   f"(seed 7); the two all-to-alls are modelled, not run"},
+            "shares": out}
+    print(json.dumps(line))
+    return 0
+
+
 def main(argv=None):
     args = parse(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -449,6 +507,8 @@ def main(argv=None):
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "shard":
+        return bench_shard(args)
 
     import numpy as np
     import torch
