@@ -288,3 +288,33 @@ def test_precompute_from_two_threads(torch_cuda):
     assert not errors, errors
     for g, w in zip(got, want):
         assert np.max(np.abs(g - w)) <= 1e-15 * np.max(np.abs(w))
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-6)])
+@pytest.mark.parametrize("kind", ["hockney", "vico_dct"])
+def test_zero_source_and_unit_impulses(torch_cuda, prec, tol, kind):
+    """Degenerate sources with an exact answer.  rho = 0 gives phi = 0 exactly.  A unit impulse at
+    grid point j gives phi_i = V K[|i - j|] (the kernel table itself, component-wise offsets):
+    checked element by element for impulses at both corners and an interior point of an
+    anisotropic grid whose rows, pencils and tiles are all ragged."""
+    torch = torch_cuda
+    n, lo, hi = (24, 12, 48), (-1.0, -0.75, -1.5), (1.0, 0.75, 1.5)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    plan = _plan(n, lo, hi, kind, prec)
+    zero = torch.zeros(n, dtype=dt, device="cuda")
+    phi0 = plan.solve(zero)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(phi0).item() == 0
+    k = kernel_octant(kind, n, lo, hi)
+    h = greens.spacing(n, lo, hi)
+    vol = h[0] * h[1] * h[2]
+    idx = np.indices(n)
+    for j in [(0, 0, 0), (n[0] - 1, n[1] - 1, n[2] - 1), (7, 5, 22)]:
+        rho = np.zeros(n)
+        rho[j] = 1.0
+        phi = to_host(plan.solve(to_dev(rho, dt)))
+        torch.cuda.synchronize()
+        want = vol * k[np.abs(idx[0] - j[0]), np.abs(idx[1] - j[1]), np.abs(idx[2] - j[2])]
+        err = np.max(np.abs(phi - want)) / np.max(np.abs(want))
+        assert err <= tol, (j, err)
+    plan.close()
