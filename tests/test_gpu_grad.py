@@ -189,3 +189,33 @@ def test_gradient_long_axis0_pencils_every_variant(torch_cuda, prec, tol):
             assert max(errs) <= tol, (n, v, errs)
             assert rel_l2(to_host(phi), phi_ref) <= tol, (n, v)
         plan.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+@pytest.mark.parametrize("kind", ["hockney", "vico_dct"])
+def test_gradient_of_unit_impulses(torch_cuda, prec, tol, kind):
+    """A unit impulse at grid point j: component a is V D_a at the offset i - j, where the table
+    D_a is odd along axis a (its octant value, negated where i_a < j_a); every variant of the
+    axis-0 pass, element by element."""
+    torch = torch_cuda
+    n, lo, hi = (24, 12, 48), (-1.0, -0.75, -1.5), (1.0, 0.75, 1.5)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    h = greens.spacing(n, lo, hi)
+    vol = h[0] * h[1] * h[2]
+    d = [_dtable(kind, n, lo, hi, a) for a in range(3)]
+    idx = np.indices(n)
+    plan = _plan(n, lo, hi, kind, prec)
+    for v in range(3):
+        plan.schedule = [0, 0, v, 0, 0]
+        for j in [(0, 0, 0), (n[0] - 1, n[1] - 1, n[2] - 1), (7, 5, 22)]:
+            rho = np.zeros(n)
+            rho[j] = 1.0
+            grad, _ = plan.solve_grad(to_dev(rho, dt))
+            torch.cuda.synchronize()
+            g = to_host(grad)
+            off = [idx[a] - j[a] for a in range(3)]
+            for a in range(3):
+                want = vol * np.sign(off[a]) * d[a][np.abs(off[0]), np.abs(off[1]), np.abs(off[2])]
+                err = np.max(np.abs(g[a] - want)) / np.max(np.abs(want))
+                assert err <= tol, (v, j, a, err)
+    plan.close()
