@@ -186,8 +186,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
 // NOUT > 0 (the gradient solve): one forward transform per pencil set, then
 // a.nout outputs (NOUT == 1: exactly one): output o multiplies by table
 // a.oghat[o] (a.ocomp[o]: 0 the potential's, 1 + a the derivative along axis
-// a) and goes to a.oout[o] (which may be S itself: the block has read its
-// pencils before it writes).  One item per launch; separate instantiations, so
+// a) and goes to a.oout[o] (which may be S itself: a block reads each pencil
+// set before it writes that set's outputs, and its two sets are different
+// rows k1 and 2 n1 - k1).  One item per launch; separate instantiations, so
 // the potential's kernel carries none of it.  With NOUT == 1 the spectrum is
 // not held through a loop (fewer registers).
 template <typename T, int L, int PID, int TC, int NQ, bool TWF = false, int NOUT = 0>
