@@ -135,6 +135,21 @@ def convolve_odd(rho: np.ndarray, d_oct: np.ndarray, h, axis: int) -> np.ndarray
     return float(h[0]) * float(h[1]) * float(h[2]) * out.reshape(n0, n1, n2)
 
 
+def convolve_odd_at(rho: np.ndarray, d_oct: np.ndarray, h, axis: int, points) -> np.ndarray:
+    """The same sum at selected output points only (any grid size; O(n^3) per point)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    n = rho.shape
+    ar = [np.arange(n[e]) for e in range(3)]
+    v = float(h[0]) * float(h[1]) * float(h[2])
+    out = np.empty(len(points))
+    for p, i in enumerate(points):
+        off = [i[e] - ar[e] for e in range(3)]
+        dd = d_oct[np.abs(off[0])[:, None, None], np.abs(off[1])[None, :, None], np.abs(off[2])[None, None, :]]
+        sgn = np.sign(off[axis]).reshape([-1 if e == axis else 1 for e in range(3)])
+        out[p] = v * float(np.sum(sgn * dd * rho))
+    return out
+
+
 def convolve_odd_loops(rho: np.ndarray, d_oct: np.ndarray, h, axis: int) -> np.ndarray:
     """The same sum as six plain loops (tiny grids only; pins ``convolve_odd``)."""
     n0, n1, n2 = rho.shape

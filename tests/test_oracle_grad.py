@@ -59,6 +59,21 @@ def test_direct_odd_sum_equals_loops():
         assert np.max(np.abs(G.convolve_odd(rho, d, h, a) - G.convolve_odd_loops(rho, d, h, a))) < 1e-15
 
 
+def test_odd_sum_at_points_equals_the_whole_grid_sum():
+    """The sampled sum (used at sizes where the whole-grid sum is out of reach) against the
+    whole-grid sum, which is itself pinned to six plain loops."""
+    n, lo, hi = (6, 8, 10), (-1.0, -1.0, -1.0), (1.0, 1.5, 2.0)
+    rho = W.random_field(n, 4)
+    h = greens.spacing(n, lo, hi)
+    pts = [(0, 0, 0), (5, 7, 9), (2, 3, 4), (5, 0, 9), (0, 7, 0)]
+    for a in range(3):
+        for d in (G.hockney_grad_octant(n, lo, hi, a), G.vico_grad_octant(n, lo, hi, a)):
+            whole = G.convolve_odd(rho, d, h, a)
+            got = G.convolve_odd_at(rho, d, h, a, pts)
+            want = np.array([whole[p] for p in pts])
+            assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(whole))
+
+
 @pytest.mark.parametrize("kind", ["hockney", "vico"])
 def test_fft_route_equals_direct_odd_sum(kind):
     n, lo, hi = (6, 8, 10), (-1.0, -1.0, -1.0), (1.0, 1.5, 2.0)
