@@ -500,7 +500,7 @@ def main(argv=None):
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are not "
-                                   "part of this build (batched and served solves shard by request)",
+                                   "implemented (batched and served solves shard by request)",
                           "n_gpus": args.gpus}))
         return 2
     if args.workload == "batch":
