@@ -221,12 +221,14 @@ def test_gradient_of_unit_impulses(torch_cuda, prec, tol, kind):
     plan.close()
 
 
-def test_gradient_full_size_512_sampled(torch_cuda):
-    """512^3 on [-1,1]^3 with the 8-Gaussian source (seed 3), Hockney-Eastwood (closed-form
-    derivative tables), autotuned: every component against the literal odd sum at sampled outputs,
-    corners included, in both precisions."""
+@pytest.mark.parametrize("lo,hi", [((-1.0,) * 3, (1.0,) * 3), ((-1.0, -1.0, -2.0), (1.0, 1.0, 2.0))],
+                         ids=["cube", "slab"])
+def test_gradient_full_size_512_sampled(torch_cuda, lo, hi):
+    """512^3 on [-1,1]^3 and on [-1,1]^2 x [-2,2] (h2 = 2 h0) with the 8-Gaussian source (seed 3),
+    Hockney-Eastwood (closed-form derivative tables), autotuned: every component against the
+    literal odd sum at sampled outputs, corners included, in both precisions."""
     torch = torch_cuda
-    n, lo, hi = 512, (-1.0,) * 3, (1.0,) * 3
+    n = 512
     rho = W.source_density(n, lo, hi, W.multiblob(seed=3, count=8))
     h = greens.spacing((n,) * 3, lo, hi)
     rng = np.random.default_rng(12)
