@@ -253,3 +253,28 @@ def test_gradient_full_size_512_sampled(torch_cuda, lo, hi):
         plan.close()
         del r, grad
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_gradient_with_column_chunks(torch_cuda, prec, tol, monkeypatch):
+    """Passes 1-3 chunk by chunk over the axis-2 columns (FSP_CHUNKS at plan creation): each chunk
+    runs the gradient's axis-0 pass (all outputs at once, or one launch per output with phi in
+    place last), every variant, against the oracle."""
+    torch = torch_cuda
+    monkeypatch.setenv("FSP_CHUNKS", "3")
+    n, lo, hi = (32, 24, 48), (-1.0, -1.0, -1.5), (1.0, 1.0, 1.5)
+    rho = W.random_field(n, 23)
+    refs = _grad_ref(rho, "vico_dct", lo, hi)
+    phi_ref = reference(rho, "vico_dct", lo, hi, use_direct=False)
+    plan = _plan(n, lo, hi, "vico_dct", prec)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    r = to_dev(rho, dt)
+    for v in range(3):
+        plan.schedule = [v] * 5
+        grad, phi = plan.solve_grad(r, want_phi=True)
+        torch.cuda.synchronize()
+        g = to_host(grad)
+        for a in range(3):
+            assert rel_l2(g[a], refs[a]) <= tol, (v, a)
+        assert rel_l2(to_host(phi), phi_ref) <= tol, v
+    plan.close()
