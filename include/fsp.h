@@ -94,44 +94,72 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out);
 
 /* Device bytes the plan needs: *ghat_bytes for the precomputed transform of
  * the Green's function (plus the plan's twiddle tables), *work_bytes for the
- * solve workspace.  Either pointer may be NULL. */
+ * solve workspace.  Either pointer may be NULL.  Section 3.3 accounts a
+ * solver's memory as the sum of its fields (values times bytes per value);
+ * these are this library's fields in that sense: the real octant of the
+ * transform of G2 instead of the full doubled-grid field, and one complex
+ * half spectrum (n0 x 2 n1 x (n2 + 1), padded rows) instead of the doubled
+ * rho2 / phi2 fields, whose zero half is never stored (Section 2.2, steps 2
+ * and 5). */
 fsp_status fsp_plan_bytes(fsp_plan p, size_t* ghat_bytes, size_t* work_bytes);
 
 /* Device bytes fsp_precompute needs transiently (freed before it returns to
- * the caller's stream order); reported for admission control. */
+ * the caller's stream order); reported for admission control.  This is the
+ * pre-computation grid of Sections 2.3 and 2.4 in float64: (4N)^3 samples for
+ * FSP_VICO, (2N+1)^3 for FSP_VICO_DCT (the memory reduction of Section 2.4),
+ * (N+1)^3 for FSP_HOCKNEY, plus one intermediate of the per-axis transforms. */
 fsp_status fsp_plan_precompute_bytes(fsp_plan p, size_t* bytes);
 
 /* Attach device memory.  ghat_dev / work_dev are caller-owned device buffers
  * of at least the sizes from fsp_plan_bytes, aligned to 256 bytes; NULL makes
  * the plan allocate (and later free) that buffer itself.  Binding again
  * replaces the previous buffers (a plan-owned buffer is freed) and clears the
- * precompute state.  The current HIP device is the plan's device. */
+ * precompute state.  The current HIP device is the plan's device.  The paper
+ * allocates its fields at solver set-up, outside the timed "Solve"
+ * (Section 3.2) and counts them in Section 3.3; binding is that set-up step,
+ * with the caller free to own the memory. */
 fsp_status fsp_plan_bind(fsp_plan p, void* ghat_dev, void* work_dev);
 
 /* Use src's precomputed transform in dst (same Green's function, grid, box,
  * alpha, g0 and precision, else FSP_ERR_INVALID_ARG).  dst then reads src's
- * buffer: src's Green's buffer must stay alive and unchanged while dst is used. */
+ * buffer: src's Green's buffer must stay alive and unchanged while dst is used.
+ * Section 2.3: the restricted G2 is computed once and reused by every later
+ * solve on the same grid; a plan of another box or spacing needs its own
+ * (Section 1: a bunch-fitted grid changes, so G2 is recomputed). */
 fsp_status fsp_plan_share_ghat(fsp_plan dst, fsp_plan src);
 
 /* Compute the transform of the Green's function on the device, in float64,
  * and store it (rounded once to the solve precision) in the plan's Green's
  * buffer, with the plan's twiddle tables (and, with FSP_WANT_GRAD, the three
- * derivative tables).  The per-axis cosine/sine contractions are float64
- * GEMMs run by rocBLAS; the first call from a host thread on a device
- * creates a rocBLAS handle for that thread and device, kept until the thread
- * ends.  Asynchronous on `stream`;
- * allocates and frees transient float64 buffers of fsp_plan_precompute_bytes
- * bytes in stream order.  Calling it again recomputes (a refresh).
+ * derivative tables).
+ *   FSP_HOCKNEY: Section 2.2 step 3 -- the kernel 1/(4 pi |x|) with the
+ *     regularised value g0 at the origin, mirror-extended to the doubled grid
+ *     (G2), then transformed (step 4); the transform of the mirror-even G2 is
+ *     a DCT-I of length n_d + 1 along each axis.
+ *   FSP_VICO: Section 2.3 -- eq. (3) sampled on the (4N)^3 frequency grid,
+ *     inverse transformed and restricted to the doubled grid, then as above.
+ *   FSP_VICO_DCT: Section 2.4 -- eq. (3) sampled on its (2N+1)^3 unique
+ *     values, inverse transformed by a DCT-I of length 2 n_d + 1 per axis
+ *     keeping the doubled grid's octant, then as above.
+ * Every per-axis transform is a dense float64 cosine (or sine) contraction
+ * run by this library's own kernels.  The result is reused by every later
+ * solve (Section 2.3); calling this again recomputes it (a refresh, needed
+ * when the grid spacing changes: Sections 1 and 2.3).  Asynchronous on
+ * `stream`; allocates and frees transient float64 buffers of
+ * fsp_plan_precompute_bytes bytes in stream order.
  * FSP_ERR_OUT_OF_MEMORY if the transient buffers cannot be allocated. */
 fsp_status fsp_precompute(fsp_plan p, void* stream);
 
 /* phi = the free-space solution for rho (both device arrays, [n0][n1][n2] in
- * the plan's precision).  phi may equal rho (in place; Section 3.3 reuses the
+ * the plan's precision): Section 2.2 steps 1, 2, 4 and 5 (zero-pad, transform,
+ * multiply by the transform of G2, inverse transform, restrict), the sum of
+ * eq. (2) over the grid.  phi may equal rho (in place; Section 3.3 reuses the
  * rho field for phi).  Asynchronous on `stream`; enqueues five kernels and
  * allocates nothing.  FSP_ERR_NOT_READY before bind + precompute. */
 fsp_status fsp_solve(fsp_plan p, const void* rho, void* phi, void* stream);
 
-/* The five passes of fsp_solve run one range at a time: passes first..last
+/* The five passes of fsp_solve (Section 2.2 steps 4-5 split by axis) run one
+ * range at a time: passes first..last
  * (0 = axis-2 real transform of rho, 1 = axis-1 forward, 2 = axis-0 forward,
  * multiply and inverse, 3 = axis-1 inverse, 4 = axis-2 inverse real transform
  * to phi).  Running 0..4 in order is fsp_solve; splitting the range lets a
@@ -162,7 +190,8 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
  * `stream`; allocates nothing. */
 fsp_status fsp_solve_grad(fsp_plan p, const void* rho, void* phi, void* grad, void* stream);
 
-/* Schedules.  Every pass has NUM_VARIANTS = 3 kernel variants (radix plan,
+/* Schedules (no passage of the paper: how this library maps each pass onto
+ * the GPU).  Every pass has NUM_VARIANTS = 3 kernel variants (radix plan,
  * threads per pencil, tile); variants[i] selects the one for pass i (0..4,
  * as in fsp_solve_passes).  The value 3 in variants[1..3] (all three) selects
  * the fused schedule for small grids with n0 == n1 (n <= 64 in float32, <= 48
@@ -178,7 +207,10 @@ fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants /* [5] */);
  * placed around that pass inside full solves (reps timed solves per variant,
  * 1 <= reps <= 8, after a warm one), keep the
  * fastest per pass in the plan and in the process-wide table used by new
- * plans of this grid and precision.  rho and phi are as in fsp_solve; on
+ * plans of this grid and precision (no passage of the paper; the schedule
+ * changes the time only, the result up to rounding order).  rho and phi are
+ * device arrays as in fsp_solve, but phi must not overlap rho
+ * (FSP_ERR_INVALID_ARG): the timed solves write phi many times.  On
  * return phi holds the solve of rho with the tuned schedule.  Synchronises
  * `stream`.  times_ms (NULL or [5 * 3 + 2]) receives the median time of each
  * variant, times_ms[pass * 3 + variant], then the time of passes 1-3 fused and
@@ -194,11 +226,14 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
 /* count independent solves (each with its own plan, and so its own
  * workspace) enqueued on one stream; plans may differ in size, precision and
  * Green's function.  rho[i] / phi[i] as in fsp_solve.  Solves of plans with
- * equal shape and precision are issued as shared kernel launches. */
+ * equal shape and precision are issued as shared kernel launches.  No passage
+ * of the paper defines this call: it is fsp_solve for many independent right-
+ * hand sides at once, each the result Section 2.2 defines. */
 fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const* rho,
                              void* const* phi, void* stream);
 
-/* A fixed set of solves replayed as one HIP graph (no per-call launch cost).
+/* A fixed set of solves replayed as one HIP graph (no per-call launch cost;
+ * no passage of the paper: a launch-cost device of this library).
  * fsp_batch_create records count (plan, rho, phi) triples with the rules of
  * fsp_solve_batched; nothing is enqueued.  The plans, their bound buffers and
  * the rho/phi arrays must stay alive and unchanged (no re-bind, no
@@ -213,11 +248,15 @@ fsp_status fsp_batch_launch(fsp_batch b, void* stream);
 fsp_status fsp_batch_destroy(fsp_batch b);
 
 /* Free the plan and any buffer it allocated.  Caller-owned buffers are not
- * touched.  Work still queued on a stream must finish first. */
+ * touched.  Work still queued on a stream must finish first.  (No passage:
+ * resource management.) */
 fsp_status fsp_plan_destroy(fsp_plan p);
 
 /* Where the transform of the Green's function sits in the Green's buffer.
- * The octant k in [0,n] (scaled by V / (8 n0 n1 n2), solve precision) is
+ * The transform of the mirror-extended G2 (Section 2.2 steps 3-4) is real and
+ * even on the doubled grid, so its octant holds all of it (the symmetry
+ * Section 2.4 uses).  The octant k in [0,n] (scaled by V / (8 n0 n1 n2),
+ * solve precision) is
  * stored in column tiles of *tile values of k2: element (k0, k1, k2) is at
  * byte *octant_offset + sizeof(real) * (((k1 * T + k2 / tile) * (n0 + 1) + k0)
  * * tile + k2 % tile), T = ceil((n2 + 1) / tile); slots with k2 > n2 hold 0.
@@ -231,9 +270,12 @@ fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* tile);
 fsp_status fsp_plan_octant_offset(fsp_plan p, int component, size_t* offset);
 
 /* Model bytes that one solve moves through HBM with this plan's schedule
- * (reads + writes of the five passes, the Green's octant included). */
+ * (reads + writes of the five passes, the Green's octant included): the
+ * memory traffic against which Section 3.4 finds the solve memory-bound. */
 fsp_status fsp_plan_model_bytes(fsp_plan p, double* bytes);
 
+/* Name of a status code, and this thread's text for the last failure (no
+ * passage: diagnostics). */
 const char* fsp_status_str(fsp_status s);
 const char* fsp_last_error(void);
 

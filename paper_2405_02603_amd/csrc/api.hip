@@ -867,6 +867,12 @@ static float median_ms(float* v, int n) {
 
 fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* stream, float* times_ms) {
   if (!p || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, "fsp_autotune: NULL argument");
+  {
+    // the timed solves write phi many times: an overlap would corrupt rho
+    const size_t field = (size_t)p->n[0] * p->n[1] * p->n[2] * p->rb;
+    const char *r = static_cast<const char*>(rho), *f = static_cast<const char*>(phi);
+    if (r < f + field && f < r + field) return fail(FSP_ERR_INVALID_ARG, "fsp_autotune: phi overlaps rho");
+  }
   if (!p->ready) return fail(FSP_ERR_NOT_READY, "fsp_autotune: plan has no bound buffers or no precomputed transform");
   if (reps < 1 || reps > 8) return fail(FSP_ERR_INVALID_ARG, "fsp_autotune: reps must be in [1, 8]");
   DeviceGuard guard;

@@ -268,8 +268,12 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   T gn[GPRE ? Lf::J : 1][GPRE ? Lf::R : 1];
 
   // k1 = p and its partner 2 n1 - p share the Green's rows; p = 0 and p = n1
-  // have no partner (uniform in a block unless the block is gathered).
-  const bool two = cok && !(p == 0 || p == a.n1);
+  // have no partner.  `second` (a second pencil set follows, with barriers) is
+  // block-uniform: gathered blocks always run it, and in the others p is the
+  // block's own; `two` is the per-lane load/store mask of that set.
+  const bool paired = !(p == 0 || p == a.n1);
+  const bool second = gathered || paired;
+  const bool two = cok && paired;
   const long long off_a = (long long)p * a.outer_stride + col;
   const long long off_b = (long long)(2 * a.n1 - p) * a.outer_stride + col;
   cx<T>* const data = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]);
@@ -373,7 +377,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       const int nout = NOUT == 1 ? 1 : a.nout;
 #pragma unroll 1
       for (int o = 0; o < nout; ++o) {
-        const bool last = set == 1 || !(gathered || two);  // no set follows this one
+        const bool last = set == 1 || !second;  // no set follows this one
         if constexpr (GPRE) {
           if (o + 1 < nout) load_g(a.oghat[o + 1], gn);
           else if (!last && nout > 1) load_g(a.oghat[0], gn);
@@ -409,7 +413,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
     }
   }
   run_set(0, raw_a, cok);
-  if (gathered || two) {  // block-uniform: barriers inside
+  if (second) {  // block-uniform: barriers inside
     if constexpr (LATE_B) load_set(data + off_b, two, raw_b);
     lds_barrier();
     run_set(1, raw_b, two);

@@ -159,7 +159,11 @@ class GpuExecutor:
         self.device = torch.device(device if device is not None else "cuda")
         self.lo, self.hi, self.alpha = tuple(lo), tuple(hi), float(alpha)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]
+        # Green's transforms are computed on a stream of their own; every solve that
+        # reads one waits for its event first (on the solving slot's stream)
+        self.pre_stream = torch.cuda.Stream(device=self.device)
         self.greens_cache: Dict[Tuple, object] = {}
+        self.greens_ready: Dict[Tuple, object] = {}
         self.idle_plans: Dict[Tuple, List[object]] = collections.defaultdict(list)
         self.source_for = source_for
         self.keep_results = keep_results
@@ -184,14 +188,29 @@ class GpuExecutor:
             job.nbytes += request_bytes(job.n, "f64", self.work_bytes(job.n, job.greens, "f64"))
 
     # -------------------------------------------------------------- plans
+    def _source_key(self, n, greens, prec):
+        return (greens, n, self.lo, self.hi, self.alpha, prec)
+
     def _source_plan(self, n, greens, prec):
-        key = (greens, n, self.lo, self.hi, self.alpha, prec)
+        """The cached plan holding the Green's transform of this shape; on a miss it is
+        precomputed on the executor's precompute stream and an event marks its end."""
+        torch = self.torch
+        key = self._source_key(n, greens, prec)
         p = self.greens_cache.get(key)
         if p is None:
-            p = self.Plan(n=n, lo=self.lo, hi=self.hi, greens=greens, prec=prec, alpha=self.alpha,
-                          device=self.device)
+            with torch.cuda.stream(self.pre_stream):
+                p = self.Plan(n=n, lo=self.lo, hi=self.hi, greens=greens, prec=prec, alpha=self.alpha,
+                              device=self.device, stream=self.pre_stream)
+                ev = torch.cuda.Event()
+                ev.record(self.pre_stream)
             self.greens_cache[key] = p
+            self.greens_ready[key] = ev
         return p
+
+    def _await_greens(self, n, greens, prec, stream) -> None:
+        """Make `stream` wait until the Green's transform of this shape is computed."""
+        self._source_plan(n, greens, prec)
+        stream.wait_event(self.greens_ready[self._source_key(n, greens, prec)])
 
     def warm(self, shapes: Sequence[Tuple[int, str, str]]) -> None:
         """Precompute the Green's transforms of the given (n, greens, prec) shapes."""
@@ -240,6 +259,7 @@ class GpuExecutor:
         with torch.cuda.stream(st):
             for j in group:
                 plan = self._plan_for(j.n, j.greens, prec)
+                self._await_greens(j.n, j.greens, prec, st)
                 host = self.source_for(j, dt)
                 rho = host.to(self.device, non_blocking=True)
                 plans.append(plan)
@@ -250,6 +270,7 @@ class GpuExecutor:
             if group[0].spot_check:
                 j = group[0]
                 p64 = self._plan_for(j.n, j.greens, "f64")
+                self._await_greens(j.n, j.greens, "f64", st)
                 r64 = rhos[0].double()
                 o64 = p64.solve(r64, stream=st)
                 diff = torch.linalg.vector_norm((outs[0].double() - o64).flatten())

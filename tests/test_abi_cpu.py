@@ -226,3 +226,20 @@ def test_footprint_against_the_paper_accounting(lib, n):
         if greens == 2:
             assert pb.value < 2 * (2 * n + 1) ** 3 * 8
         lib.fsp_plan_destroy(h)
+
+
+def test_autotune_rejects_aliased_rho_phi(lib):
+    """The tuning solves write phi many times, so phi may not overlap rho; checked on
+    the host before the plan's state."""
+    st, h = _create(lib, _desc(n=16))
+    assert st == _lib.FSP_OK
+    base = 1 << 20
+    field = 16 ** 3 * 4
+    for off in (0, 4, field - 4):
+        r = lib.fsp_autotune(h, ctypes.c_void_p(base), ctypes.c_void_p(base + off), 2, None, None)
+        assert r == _lib.FSP_ERR_INVALID_ARG, off
+        assert b"overlaps" in lib.fsp_last_error()
+    # disjoint buffers get past the alias check (and stop at the unbound plan)
+    r = lib.fsp_autotune(h, ctypes.c_void_p(base), ctypes.c_void_p(base + field), 2, None, None)
+    assert r == _lib.FSP_ERR_NOT_READY
+    lib.fsp_plan_destroy(h)

@@ -9,7 +9,7 @@ import pytest
 
 import workloads as W
 
-from gpu_util import reference, rel_l2, to_dev, to_host
+from gpu_util import F32_ELEM, F64_TOL, elem_err, reference, rel_l2, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -58,11 +58,13 @@ def test_batched_equals_solo_bitwise(torch_cuda):
         solo = p.solve(r)
         torch.cuda.synchronize()
         assert torch.equal(solo, o)
-    # and the results are right
-    for i in (0, 5, 11):
+    # and every result is right: each item against the oracle at its own size and kernel
+    for i, it in enumerate(items):
         kind = ("vico_dct", "hockney")[i % 2]
-        ref = reference(host[i], kind, items[i].lo, items[i].hi, use_direct=False)
-        assert rel_l2(to_host(outs[i]), ref) <= 1e-6
+        ref = reference(host[i], kind, it.lo, it.hi, use_direct=False)
+        got = to_host(outs[i])
+        assert rel_l2(got, ref) <= 1e-6, (i, it.n, kind)
+        assert elem_err(got, ref) <= F32_ELEM, (i, it.n, kind)
 
 
 def test_more_than_one_launch_group(torch_cuda):
@@ -70,20 +72,24 @@ def test_more_than_one_launch_group(torch_cuda):
     torch = torch_cuda
     from paper_2405_02603_amd import solve_batched
     items = _mix(20, seed=9, sizes=(32,))
-    plans, rhos, _ = _plans_and_inputs(torch, items, prec="f64")
+    plans, rhos, host = _plans_and_inputs(torch, items, prec="f64")
     outs = solve_batched(plans, rhos)
     torch.cuda.synchronize()
     for p, r, o in zip(plans, rhos, outs):
         assert torch.equal(p.solve(r), o)
+    for it, h, o in zip(items, host, outs):
+        assert rel_l2(to_host(o), reference(h, "vico_dct", it.lo, it.hi, use_direct=False)) <= F64_TOL
 
 
 def test_graph_replays_match_eager(torch_cuda):
     torch = torch_cuda
     from paper_2405_02603_amd import Batch
     items = _mix(12, seed=5, sizes=(32, 48, 64))
-    plans, rhos, _ = _plans_and_inputs(torch, items)
+    plans, rhos, host = _plans_and_inputs(torch, items)
     eager = [p.solve(r) for p, r in zip(plans, rhos)]
     torch.cuda.synchronize()
+    for it, h, e in zip(items, host, eager):
+        assert rel_l2(to_host(e), reference(h, "vico_dct", it.lo, it.hi, use_direct=False)) <= 1e-6
     batch = Batch(plans, rhos)
     for rep in range(4):
         for o in batch.outs:

@@ -19,7 +19,7 @@ import pytest
 import workloads as W
 from oracle import direct, exact, greens
 
-from gpu_util import kernel_octant, reference, rel_l2, to_dev, to_host
+from gpu_util import F32_ELEM, F64_ELEM, elem_err, kernel_octant, reference, rel_l2, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -122,11 +122,15 @@ def test_full_size_256(torch_cuda, kind, box):
     src = W.multiblob(seed=3, count=8)
     rho = W.source_density(n, *box, src)
     ref = reference(rho, kind, *box, use_direct=False)
-    e64 = rel_l2(_solve(torch_cuda, n, box, kind, "f64", rho, tune=True), ref)
-    e32 = rel_l2(_solve(torch_cuda, n, box, kind, "f32", rho, tune=True), ref)
-    print("full 256", kind, box[1], f"f64 {e64:.3e} f32 {e32:.3e}")
-    assert e64 <= F64_TOL
-    assert e32 <= F32_TOL
+    p64 = _solve(torch_cuda, n, box, kind, "f64", rho, tune=True)
+    e64, m64 = rel_l2(p64, ref), elem_err(p64, ref)
+    del p64
+    p32 = _solve(torch_cuda, n, box, kind, "f32", rho, tune=True)
+    e32, m32 = rel_l2(p32, ref), elem_err(p32, ref)
+    del p32
+    print("full 256", kind, box[1], f"f64 {e64:.3e} (elem {m64:.3e}) f32 {e32:.3e} (elem {m32:.3e})")
+    assert e64 <= F64_TOL and m64 <= F64_ELEM
+    assert e32 <= F32_TOL and m32 <= F32_ELEM
 
 
 def _strided_closed_form(n, box, src, s):
@@ -162,8 +166,10 @@ def test_full_size_512(torch_cuda, box):
         del phi
         phi = _solve(torch_cuda, n, box, "vico_dct", prec, rho)
         e = rel_l2(phi[::4, ::4, ::4], closed)
-        print("full 512", box[1], prec, f"vico vs closed form {e:.3e}")
+        m = elem_err(phi[::4, ::4, ::4], closed)
+        print("full 512", box[1], prec, f"vico vs closed form {e:.3e} (elem {m:.3e})")
         assert e <= tol_cf, (prec, e)
+        assert m <= 6 * tol_cf, (prec, m)
         del phi
 
 

@@ -259,10 +259,14 @@ def test_gradient_full_size_512_sampled(torch_cuda, lo, hi):
 def test_gradient_with_column_chunks(torch_cuda, prec, tol, monkeypatch):
     """Passes 1-3 chunk by chunk over the axis-2 columns (FSP_CHUNKS at plan creation): each chunk
     runs the gradient's axis-0 pass (all outputs at once, or one launch per output with phi in
-    place last), every variant, against the oracle."""
+    place last), every variant, against the oracle.  193 columns: in float32 (chunk step 64,
+    the axis-1 tile of 48-point pencils) the chunks are [0, 128) and [128, 193), in float64
+    (step 32) [0, 96), [96, 192) and [192, 193); both last chunks hold one column past a whole
+    axis-0 tile, which is gathered over k1 pairs (FSP_CONV_GATHER_MIN=0)."""
     torch = torch_cuda
     monkeypatch.setenv("FSP_CHUNKS", "3")
-    n, lo, hi = (32, 24, 48), (-1.0, -1.0, -1.5), (1.0, 1.0, 1.5)
+    monkeypatch.setenv("FSP_CONV_GATHER_MIN", "0")
+    n, lo, hi = (32, 24, 192), (-1.0, -1.0, -1.5), (1.0, 1.0, 1.5)
     rho = W.random_field(n, 23)
     refs = _grad_ref(rho, "vico_dct", lo, hi)
     phi_ref = reference(rho, "vico_dct", lo, hi, use_direct=False)

@@ -10,6 +10,8 @@ import pytest
 
 import workloads as W
 
+from gpu_util import F32_ELEM, elem_err, reference, rel_l2, to_host
+
 pytestmark = pytest.mark.gpu
 
 SIZES = (32, 48, 64, 96)
@@ -44,17 +46,28 @@ def _jobs(count, rate, seed, spot_every=10):
     return jobs
 
 
+def _own_sources(torch, jobs):
+    """Each request's own source (8 Gaussians drawn per request), host float64 and pinned copies."""
+    host, pinned = {}, {}
+    for j in jobs:
+        rho = W.source_density(j.n, (-1.0,) * 3, (1.0,) * 3, W.multiblob(seed=1000 + j.rid))
+        host[j.rid] = rho
+        for dt in (torch.float32, torch.float64):
+            pinned[(j.rid, dt)] = torch.from_numpy(rho).to(dt).pin_memory()
+    return host, pinned
+
+
 def test_serve_mix_equals_alone(torch_cuda):
     torch = torch_cuda
     from paper_2405_02603_amd import Plan
     from paper_2405_02603_amd.serve import GpuExecutor, Server
 
-    pool = _sources(torch)
-    ex = GpuExecutor(slots=4, source_for=lambda j, dt: pool[(j.n, dt)], keep_results=True)
+    jobs = _jobs(48, rate=400.0, seed=5)
+    host, pinned = _own_sources(torch, jobs)
+    ex = GpuExecutor(slots=4, source_for=lambda j, dt: pinned[(j.rid, dt)], keep_results=True)
     ex.warm([(n, g, p) for n in SIZES for g in ("hockney", "vico_dct") for p in ("f32", "f64")])
     budget = 1 << 30
     srv = Server(ex, budget_bytes=budget, slots=4)
-    jobs = _jobs(48, rate=400.0, seed=5)
     rep = srv.run(jobs)
     torch.cuda.synchronize()
     assert rep["done"] == len(jobs), rep
@@ -67,9 +80,35 @@ def test_serve_mix_equals_alone(torch_cuda):
     assert -0.5 <= rep["seen_lag_ms"]["min"] and rep["seen_lag_ms"]["p50"] < 20.0, rep["seen_lag_ms"]
     for j in jobs:
         alone = Plan(n=j.n, lo=(-1.0,) * 3, hi=(1.0,) * 3, greens=j.greens, prec="f32")
-        phi = alone.solve(pool[(j.n, torch.float32)].to("cuda"))
+        phi = alone.solve(pinned[(j.rid, torch.float32)].to("cuda"))
         torch.cuda.synchronize()
         assert torch.equal(phi, ex.results[j.rid]), f"request {j.rid} differs in the mix"
+        # and the served result is the oracle's, at its own size, kernel and source
+        ref = reference(host[j.rid], j.greens, (-1.0,) * 3, (1.0,) * 3, use_direct=False)
+        got = to_host(ex.results[j.rid])
+        assert rel_l2(got, ref) <= 1e-6, (j.rid, j.n, j.greens)
+        assert elem_err(got, ref) <= F32_ELEM, (j.rid, j.n, j.greens)
+
+
+def test_serve_cold_cache_two_slots_same_shape(torch_cuda):
+    """No warm-up: the first requests of a shape find no Green's transform, and several
+    requests of that shape run at once on different slots (one job per launch).  Each
+    solve waits for the precompute it reads, so every result is the oracle's."""
+    torch = torch_cuda
+    from paper_2405_02603_amd.serve import GpuExecutor, Job, Server
+
+    jobs = [Job(rid=i, t_arrival=0.0, n=(64 if i % 3 else 48), greens=("vico_dct" if i % 2 else "hockney"))
+            for i in range(12)]
+    host, pinned = _own_sources(torch, jobs)
+    ex = GpuExecutor(slots=3, source_for=lambda j, dt: pinned[(j.rid, dt)], keep_results=True)
+    srv = Server(ex, budget_bytes=1 << 30, slots=3, max_fold=1)
+    rep = srv.run(jobs)
+    torch.cuda.synchronize()
+    assert rep["done"] == len(jobs), rep
+    assert len({j.slot for j in jobs}) > 1
+    for j in jobs:
+        ref = reference(host[j.rid], j.greens, (-1.0,) * 3, (1.0,) * 3, use_direct=False)
+        assert rel_l2(to_host(ex.results[j.rid]), ref) <= 1e-6, (j.rid, j.n, j.greens)
 
 
 def test_serve_rejects_over_budget(torch_cuda):
