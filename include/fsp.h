@@ -247,6 +247,26 @@ fsp_status fsp_batch_create(int count, const fsp_plan* plans, const void* const*
 fsp_status fsp_batch_launch(fsp_batch b, void* stream);
 fsp_status fsp_batch_destroy(fsp_batch b);
 
+/* fsp_solve with no device allocation and no plan workspace, for callers
+ * that cannot allocate device memory at solve time (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc after set-up).
+ * The five passes run on a workspace inside the library: one static device
+ * array of FSP_STATIC_SCRATCH_BYTES per GPU, held until the process ends.
+ * Plans whose one-spectrum workspace (fsp_plan_bytes' work_bytes, a quarter
+ * of it on a plan with FSP_WANT_GRAD) exceeds it are rejected with
+ * FSP_ERR_UNSUPPORTED_SIZE, on the host, before the plan's state is checked
+ * and before anything is enqueued: grids up to 128^3 fit in both precisions.  The plan must be bound and precomputed (its Green's
+ * buffer is read; its own workspace is not used); rho and phi as in fsp_solve
+ * (phi may equal rho).  Every call on one GPU shares that GPU's array: two
+ * calls whose work overlaps on one GPU (any plans, any streams) race and both
+ * results are undefined, so callers serialise them (one stream, or events).
+ * Nothing in the array needs clearing between calls: each solve writes every
+ * element it later reads.  Asynchronous on `stream`; the first call on a
+ * device (or the first fsp_plan_bind there) looks up that device's copy of the
+ * array. */
+#define FSP_STATIC_SCRATCH_BYTES (80u * 1024u * 1024u)
+fsp_status fsp_solve_static(fsp_plan p, const void* rho, void* phi, void* stream);
+
 /* Free the plan and any buffer it allocated.  Caller-owned buffers are not
  * touched.  Work still queued on a stream must finish first.  (No passage:
  * resource management.) */

@@ -188,6 +188,21 @@ class Plan:
                                       _stream_ptr(stream)), "fsp_solve")
         return out
 
+    def solve_static(self, rho, out=None, stream=None):
+        """As ``solve`` but on the library's static per-GPU workspace (fsp_solve_static):
+        the call allocates no device memory.  ``out`` must be given when the caller
+        cannot allocate; calls that overlap on one GPU race (serialise them)."""
+        torch = _torch()
+        self._check_field(rho, "rho")
+        if out is None:
+            out = torch.empty_like(rho)
+        self._check_field(out, "out")
+        with torch.cuda.device(self.device):
+            check(self._lib.fsp_solve_static(self._h, ctypes.c_void_p(rho.data_ptr()),
+                                             ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+                  "fsp_solve_static")
+        return out
+
     def solve_grad(self, rho, grad=None, phi=None, want_phi: bool = False, stream=None):
         """grad = (d phi/dx0, d phi/dx1, d phi/dx2) as a [3][n0][n1][n2] tensor, and phi when
         ``phi`` is given or ``want_phi``; returns (grad, phi or None).  See fsp_solve_grad."""

@@ -33,8 +33,11 @@ EXPORTS = (
     "fsp_plan_ghat_layout", "fsp_plan_model_bytes", "fsp_status_str", "fsp_last_error", "fsp_version",
     "fsp_batch_create", "fsp_batch_launch", "fsp_batch_destroy",
     "fsp_plan_get_schedule", "fsp_plan_set_schedule", "fsp_autotune",
-    "fsp_solve_grad", "fsp_plan_octant_offset",
+    "fsp_solve_grad", "fsp_plan_octant_offset", "fsp_solve_static",
 )
+
+# size of the library's static workspace used by fsp_solve_static (FSP_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 80 * 1024 * 1024
 
 
 class PlanDesc(ctypes.Structure):
@@ -81,6 +84,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "fsp_plan_share_ghat": (c_int, [P, P]),
         "fsp_precompute": (c_int, [P, P]),
         "fsp_solve": (c_int, [P, P, P, P]),
+        "fsp_solve_static": (c_int, [P, P, P, P]),
         "fsp_solve_passes": (c_int, [P, P, P, c_int, c_int, P]),
         "fsp_solve_batched": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), P]),
         "fsp_plan_destroy": (c_int, [P]),

@@ -210,6 +210,32 @@ struct DeviceGuard {
   }
 };
 
+// Workspace of fsp_solve_static: one array per GPU (every device that loads
+// this code object holds its own copy until the process ends).  In host code
+// the name stands for no device address: the address of a device's copy comes
+// from hipGetSymbolAddress with that device current (scratch_address).
+static __device__ __align__(256) unsigned char scratch[FSP_STATIC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device -> address of its copy of scratch
+
+// The device address of `scratch` on device dev, which must be current.
+// Looked up once per device and kept.
+hipError_t scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct fsp_plan_s {
@@ -467,6 +493,12 @@ fsp_status fsp_plan_bind(fsp_plan p, void* ghat_dev, void* work_dev) {
   if (e != hipSuccess) return fail_hip(e, "fsp_plan_bind: hipGetDevice");
   release_buffers(p);
   p->device = dev;
+  if (p->work1_bytes <= FSP_STATIC_SCRATCH_BYTES) {
+    // set-up time: find this device's fsp_solve_static workspace now, so that
+    // call does no lookup later (a failure here is retried, and reported, there)
+    void* ws = nullptr;
+    if (scratch_address(dev, &ws) != hipSuccess) (void)hipGetLastError();
+  }
   if (ghat_dev) {
     p->ghat = ghat_dev;
   } else {
@@ -761,6 +793,27 @@ fsp_status fsp_solve(fsp_plan p, const void* rho, void* phi, void* stream) {
   hipError_t e = guard.enter(p->device);
   if (e != hipSuccess) return fail_hip(e, "fsp_solve: hipSetDevice");
   return solve_one(p, rho, phi, reinterpret_cast<hipStream_t>(stream));
+}
+
+fsp_status fsp_solve_static(fsp_plan p, const void* rho, void* phi, void* stream) {
+  if (!p || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_static: NULL argument");
+  if (p->work1_bytes > FSP_STATIC_SCRATCH_BYTES)
+    return fail(FSP_ERR_UNSUPPORTED_SIZE, "fsp_solve_static: the plan's workspace of " +
+                                              std::to_string(p->work1_bytes) + " bytes exceeds the static " +
+                                              std::to_string((size_t)FSP_STATIC_SCRATCH_BYTES) + "-byte scratch");
+  if (!p->ready) return fail(FSP_ERR_NOT_READY, "fsp_solve_static: plan has no bound buffers or no precomputed transform");
+  DeviceGuard guard;
+  hipError_t e = guard.enter(p->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_solve_static: hipSetDevice");
+  void* ws = nullptr;
+  e = scratch_address(p->device, &ws);
+  if (e != hipSuccess) return fail_hip(e, "fsp_solve_static: hipGetSymbolAddress of the scratch array");
+  fsp::SolveGeom g = group_geom(p);
+  add_item(g, p, rho, phi);
+  g.work[0] = ws;  // the plan's own workspace is not touched
+  e = run_group(g, p->d.prec == FSP_F64, 0, 4, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail_hip(e, "fsp_solve_static");
+  return FSP_OK;
 }
 
 fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, int last, void* stream) {

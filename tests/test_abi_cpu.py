@@ -228,6 +228,31 @@ def test_footprint_against_the_paper_accounting(lib, n):
         lib.fsp_plan_destroy(h)
 
 
+def test_static_solve_rejects_oversize_on_the_host(lib):
+    """fsp_solve_static checks the plan's workspace against its static scratch before
+    anything touches a device: a 256^2 x 128 float32 plan is too big, 128^3 float64 fits
+    (and is then only 'not ready', since it was never bound)."""
+    dummy = ctypes.c_void_p(256)
+    st, h = _create(lib, _desc(n=(256, 256, 128), greens=0, prec=0))
+    assert st == _lib.FSP_OK
+    assert lib.fsp_solve_static(h, dummy, dummy, None) == _lib.FSP_ERR_UNSUPPORTED_SIZE
+    assert b"scratch" in lib.fsp_last_error()
+    lib.fsp_plan_destroy(h)
+    st, h = _create(lib, _desc(n=128, greens=0, prec=1))
+    wb = ctypes.c_size_t()
+    assert lib.fsp_plan_bytes(h, None, ctypes.byref(wb)) == _lib.FSP_OK
+    assert wb.value <= _lib.STATIC_SCRATCH_BYTES
+    assert lib.fsp_solve_static(h, dummy, dummy, None) == _lib.FSP_ERR_NOT_READY
+    lib.fsp_plan_destroy(h)
+    assert lib.fsp_solve_static(None, dummy, dummy, None) == _lib.FSP_ERR_INVALID_ARG
+
+
+def test_static_scratch_size_matches_header():
+    text = open(os.path.join(ROOT, "include", "fsp.h")).read()
+    m = re.search(r"#define FSP_STATIC_SCRATCH_BYTES \((\d+)u \* 1024u \* 1024u\)", text)
+    assert m and int(m.group(1)) * 1024 * 1024 == _lib.STATIC_SCRATCH_BYTES
+
+
 def test_autotune_rejects_aliased_rho_phi(lib):
     """The tuning solves write phi many times, so phi may not overlap rho; checked on
     the host before the plan's state."""
