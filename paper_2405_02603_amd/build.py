@@ -58,8 +58,7 @@ def build(jobs: int = 4, debug: bool = False, verbose: bool = False, defines=(),
     with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         objs = list(ex.map(lambda s: compile_one(s, debug, defines, build_dir), SOURCES))
     tmp = out + ".tmp"
-    # rocBLAS: the float64 dense contractions of the Green's-table precompute
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-lrocblas", "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

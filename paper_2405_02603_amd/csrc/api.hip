@@ -11,6 +11,7 @@
 #include <string>
 #include <array>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
 #include <vector>
@@ -26,8 +27,10 @@ hipError_t greens_he_kernel(double* K, const int n[3], const double h[3], double
 hipError_t greens_he_grad_kernel(double* D, const int n[3], const double h[3], int axis, hipStream_t s);
 hipError_t greens_vico_spectrum(double* G, const int samples[3], const double f[3], double L, bool fft_order,
                                 hipStream_t s);
-hipError_t greens_contract_axis(const double* X, double* Y, const double* C, const long long dims[3], int axis,
-                                int nout, hipStream_t s);
+hipError_t greens_contract_axis(const double* X, double* Y, const double* packed, int period,
+                                const long long dims[3], int axis, int nout, hipStream_t s);
+void greens_pack_contract(std::vector<double>& out, const std::vector<double>& ce, const std::vector<double>* co,
+                          int nout, int kin, int period);
 hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int tile, double scale,
                                hipStream_t s);
 int conv_tile_f32(int L);
@@ -126,18 +129,31 @@ struct TrigTable {
   }
 };
 
-// DCT-I rows m < nout of a length period+1 transform: C[m][l] = w_l cos(pi l m / period),
-// w_0 = w_period = 1, else 2.
-void dct1_matrix(std::vector<double>& C, int nout, int period) {
-  const int nin = period + 1;
+// DCT-I rows m < nout of a length period + 1 transform, C[m][l] = w_l cos(pi l m / period)
+// (w = 1 at l = 0 and l = period, else 2), folded for the contraction kernel,
+// which pairs inputs l and period - l: Ce[r][l] = w_l cos(pi l (2r) / period), l in [0, period / 2], acts
+// on the sums X[l] + X[period - l] (X[period / 2] alone at l = period / 2), and
+// Co[r][l] = w_l cos(pi l (2r + 1) / period), l in [0, period / 2), on the
+// differences X[l] - X[period - l]; the cosines of l and period - l agree up to
+// (-1)^m, so this is the whole sum with half the products.
+void dct1_fold_matrices(std::vector<double>& Ce, std::vector<double>& Co, int nout, int period) {
+  const int half = period / 2;
   const TrigTable tt(period);
-  C.resize((size_t)nout * nin);
-  for (int m = 0; m < nout; ++m)
-    for (int l = 0; l < nin; ++l) {
-      const long long t = ((long long)l * m) % (2LL * period);
-      const long double w = (l == 0 || l == period) ? 1.0L : 2.0L;
-      C[(size_t)m * nin + l] = (double)(w * tt.c[t]);
+  const int re = (nout + 1) / 2, ro = nout / 2;
+  Ce.assign((size_t)re * (half + 1), 0.0);
+  Co.assign((size_t)ro * half, 0.0);
+  for (int m = 0; m < nout; ++m) {
+    const bool even = m % 2 == 0;
+    const int k = even ? half + 1 : half;
+    double* row = even ? &Ce[(size_t)(m / 2) * k] : &Co[(size_t)(m / 2) * k];
+    // angle index l m mod 2 period, stepped; w c is exact in double for w = 1, 2
+    long long t = 0;
+    for (int l = 0; l < k; ++l) {
+      row[l] = (l == 0 ? 1.0 : 2.0) * (double)tt.c[t];
+      t += m;
+      if (t >= 2LL * period) t %= 2LL * period;
     }
+  }
 }
 
 // Octant rows of the inverse DFT of real, even data on a grid of s = 4n points:
@@ -340,6 +356,15 @@ const char* fsp_last_error(void) { return g_err.c_str(); }
 
 const char* fsp_version(void) { return "fsp 0.1.0 gfx950"; }
 
+// Doubles in the matrix image of one axis contraction (fsp::greens_pack_contract):
+// nout rows over kin inputs, folded when period > 0.
+static size_t image_elems(int nout, int kin, int period) {
+  const bool fold = period > 0;
+  const size_t re = fold ? (nout + 1) / 2 : nout, ro = fold ? nout / 2 : 0;
+  const size_t ke = fold ? period / 2 + 1 : kin;
+  return (ke + 15) / 16 * ((re + 15) / 16 + (ro + 15) / 16) * 256;
+}
+
 fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
   if (!desc || !out) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: NULL argument");
   *out = nullptr;
@@ -420,22 +445,28 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
   }
   // transient float64 precompute buffers (two ping-pong arrays) + cosine matrices
   const size_t n0 = p->n[0], n1 = p->n[1], n2 = p->n[2];
-  size_t a = 0, b = 0, cm = 0;
+  size_t a = 0, b = 0;
   if (d.greens == FSP_HOCKNEY) {
     a = b = (n0 + 1) * (n1 + 1) * (n2 + 1);
-    cm = (n0 + 1) * (n0 + 1) + (n1 + 1) * (n1 + 1) + (n2 + 1) * (n2 + 1);
   } else if (d.greens == FSP_VICO_DCT) {
     a = (2 * n0 + 1) * (2 * n1 + 1) * (2 * n2 + 1);
     b = (2 * n1 + 1) * (2 * n2 + 1) * (n0 + 1);
-    cm = (n0 + 1) * (2 * n0 + 1) + (n1 + 1) * (2 * n1 + 1) + (n2 + 1) * (2 * n2 + 1) + (n0 + 1) * (n0 + 1) +
-         (n1 + 1) * (n1 + 1) + (n2 + 1) * (n2 + 1);
   } else {
     a = 64 * n0 * n1 * n2;
     b = 16 * n1 * n2 * (n0 + 1);
-    cm = (n0 + 1) * 4 * n0 + (n1 + 1) * 4 * n1 + (n2 + 1) * 4 * n2 + (n0 + 1) * (n0 + 1) + (n1 + 1) * (n1 + 1) +
-         (n2 + 1) * (n2 + 1);
   }
-  p->pre_bytes = align_up(a * 8, 256) + align_up(b * 8, 256) + align_up(cm * 8 * (p->grad ? 4 : 1), 256);
+  size_t cm = 0;  // matrix images of every component (the same sizes component_matrices builds)
+  for (int comp = 0; comp < (p->grad ? 4 : 1); ++comp)
+    for (int ax = 0; ax < 3; ++ax) {
+      const int m = p->n[ax];
+      const bool deriv = comp == ax + 1;
+      if (d.greens == FSP_VICO_DCT)
+        cm += deriv ? image_elems(m + 1, 2 * m + 1, 0) : image_elems(m + 1, 2 * m + 1, 2 * m);
+      else if (d.greens == FSP_VICO)
+        cm += image_elems(m + 1, 4 * m, 0);
+      cm += deriv ? image_elems(m + 1, m + 1, 0) : image_elems(m + 1, m + 1, m);
+    }
+  p->pre_bytes = align_up(a * 8, 256) + align_up(b * 8, 256) + align_up(cm * 8, 256);
   *out = p;
   g_err.clear();
   return FSP_OK;
@@ -543,42 +574,99 @@ fsp_status fsp_plan_share_ghat(fsp_plan dst, fsp_plan src) {
   return FSP_OK;
 }
 
+// Matrix images depend only on the transform's sizes (and, for the derivative
+// forms, on the frequency step kfac), not on the plan: each is built once per
+// process and shared.  The cache is cleared when it holds many images (plans
+// with FSP_WANT_GRAD on ever-changing boxes); images in use stay alive.
+extern "C++" {
+using ImagePtr = std::shared_ptr<const std::vector<double>>;
+std::mutex g_image_mu;
+std::map<std::tuple<int, int, int, int, uint64_t>, ImagePtr> g_images;
+
+template <class Build>
+ImagePtr cached_image(int kind, int nout, int kin, int period, double kfac, Build build) {
+  uint64_t bits = 0;
+  std::memcpy(&bits, &kfac, sizeof bits);
+  const auto key = std::make_tuple(kind, nout, kin, period, bits);
+  {
+    std::lock_guard<std::mutex> lk(g_image_mu);
+    auto it = g_images.find(key);
+    if (it != g_images.end()) return it->second;
+  }
+  auto img = std::make_shared<std::vector<double>>();
+  build(*img);
+  std::lock_guard<std::mutex> lk(g_image_mu);
+  if (g_images.size() >= 256) g_images.clear();
+  g_images[key] = img;
+  return img;
+}
+}  // extern "C++"
+
+// One axis contraction of a precompute: the offset of its matrix image
+// (fsp::greens_pack_contract) and, for a DCT-I run folded, its period.
+struct AxisOp {
+  size_t off = 0;
+  int period = 0;  // > 0: folded DCT-I of this period
+};
+
 // Matrices of one component's precompute, in the order they are used: for
 // Vico-Greengard the three spectrum -> kernel contractions, then the three
 // kernel -> transform contractions.  Component 0 is the potential; component
 // 1 + a the derivative along axis a, whose axis-a matrices are the sine forms.
-static void component_matrices(const fsp_plan_s* p, int comp, std::vector<double>& cm, std::vector<size_t>& moff) {
+static void component_matrices(const fsp_plan_s* p, int comp, std::vector<double>& cm, std::vector<AxisOp>& ops) {
   const int* n = p->n;
   const int gk = p->d.greens;
   const int ax = comp - 1;
-  std::vector<double> tmp;
-  auto add = [&](const std::vector<double>& m) {
-    moff.push_back(cm.size());
-    cm.insert(cm.end(), m.begin(), m.end());
+  enum { IMG_DCT1, IMG_SINE_K, IMG_DFT_COS, IMG_DFT_SIN_K, IMG_DST1 };
+  auto push = [&](const ImagePtr& img, int period) {
+    AxisOp op;
+    op.period = period;
+    op.off = cm.size();
+    cm.insert(cm.end(), img->begin(), img->end());
+    ops.push_back(op);
+  };
+  // a plain matrix of nout rows over kin inputs, or a DCT-I run folded
+  auto add = [&](int kind, int nout, int kin, double kfac, void (*fill)(std::vector<double>&, int, int, double)) {
+    push(cached_image(kind, nout, kin, 0, kfac,
+                      [&](std::vector<double>& img) {
+                        std::vector<double> c;
+                        fill(c, nout, kin, kfac);
+                        fsp::greens_pack_contract(img, c, nullptr, nout, kin, 0);
+                      }),
+         0);
+  };
+  auto add_dct1 = [&](int nout, int period) {
+    push(cached_image(IMG_DCT1, nout, period + 1, period, 0.0,
+                      [&](std::vector<double>& img) {
+                        std::vector<double> ce, co;
+                        dct1_fold_matrices(ce, co, nout, period);
+                        fsp::greens_pack_contract(img, ce, &co, nout, period + 1, period);
+                      }),
+         period);
   };
   if (gk == FSP_VICO_DCT) {
     for (int a = 0; a < 3; ++a) {
       if (a == ax)
-        sine_k_matrix(tmp, n[a] + 1, 2 * n[a], M_PI / (2.0 * n[a] * p->h[a]));
+        add(IMG_SINE_K, n[a] + 1, 2 * n[a] + 1, M_PI / (2.0 * n[a] * p->h[a]),
+            [](std::vector<double>& c, int nout, int kin, double kf) { sine_k_matrix(c, nout, kin - 1, kf); });
       else
-        dct1_matrix(tmp, n[a] + 1, 2 * n[a]);
-      add(tmp);
+        add_dct1(n[a] + 1, 2 * n[a]);
     }
   } else if (gk == FSP_VICO) {
     for (int a = 0; a < 3; ++a) {
       if (a == ax)
-        dft_sin_k_matrix(tmp, n[a] + 1, 4 * n[a], 2.0 * M_PI / (4.0 * n[a] * p->h[a]));
+        add(IMG_DFT_SIN_K, n[a] + 1, 4 * n[a], 2.0 * M_PI / (4.0 * n[a] * p->h[a]),
+            [](std::vector<double>& c, int nout, int kin, double kf) { dft_sin_k_matrix(c, nout, kin, kf); });
       else
-        dft_cos_matrix(tmp, n[a] + 1, 4 * n[a]);
-      add(tmp);
+        add(IMG_DFT_COS, n[a] + 1, 4 * n[a], 0.0,
+            [](std::vector<double>& c, int nout, int kin, double) { dft_cos_matrix(c, nout, kin); });
     }
   }
   for (int a = 0; a < 3; ++a) {
     if (a == ax)
-      dst1_matrix(tmp, n[a]);
+      add(IMG_DST1, n[a] + 1, n[a] + 1, 0.0, [](std::vector<double>& c, int, int kin, double) { dst1_matrix(c, kin - 1); });
     else
-      dct1_matrix(tmp, n[a] + 1, n[a]);
-    add(tmp);
+      add_dct1(n[a] + 1, n[a]);
   }
 }
 
@@ -595,9 +683,9 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
   // all components' matrices, uploaded once (the host image outlives the copy)
   std::vector<double>& cm = p->cmat_host;
   cm.clear();
-  std::vector<size_t> moff;
-  for (int c = 0; c < ncomp; ++c) component_matrices(p, c, cm, moff);
-  const size_t per_comp = moff.size() / ncomp;
+  std::vector<AxisOp> ops;
+  for (int c = 0; c < ncomp; ++c) component_matrices(p, c, cm, ops);
+  const size_t per_comp = ops.size() / ncomp;
   const size_t n0 = n[0], n1 = n[1], n2 = n[2];
   size_t a_elems, b_elems;
   if (gk == FSP_HOCKNEY) {
@@ -630,7 +718,9 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
     int axis = 0;
     auto contract = [&](int nout) {
       // axes in order 0, 1, 2: dims[axis] -> nout, layout order unchanged
-      if (e == hipSuccess) e = fsp::greens_contract_axis(X, Y, C + moff[mi], dims, axis, nout, s);
+      const AxisOp& op = ops[mi];
+      if (e == hipSuccess)
+        e = fsp::greens_contract_axis(X, Y, C + op.off, op.period, dims, axis, nout, s);
       ++mi;
       dims[axis] = nout;
       axis = (axis + 1) % 3;
