@@ -312,6 +312,105 @@ struct Dft<32, INV, T> {
   }
 };
 
+// ---------------------------------------------------------------- pruned butterflies
+// exp(-2 pi i r / R) = (tw_c, tw_s) for r < R / 2, R <= 32 (forward sign; the
+// inverse conjugates through mul_const<INV>).
+__host__ __device__ constexpr double tw_cos(int r, int R) {
+  // cos(2 pi r / R) for the 16 angles r / R in [0, 1/2) with R | 32
+  constexpr double c32[16] = {1.0,
+                              0.98078528040323044913,
+                              0.92387953251128675613,
+                              0.83146961230254523708,
+                              0.70710678118654752440,
+                              0.55557023301960222474,
+                              0.38268343236508977173,
+                              0.19509032201612826785,
+                              0.0,
+                              -0.19509032201612826785,
+                              -0.38268343236508977173,
+                              -0.55557023301960222474,
+                              -0.70710678118654752440,
+                              -0.83146961230254523708,
+                              -0.92387953251128675613,
+                              -0.98078528040323044913};
+  return c32[r * (32 / R)];
+}
+__host__ __device__ constexpr double tw_sin(int r, int R) {
+  // sin(2 pi r / R) = cos(2 pi (r / R - 1/4)); for r / R < 1/4 use the cosine of the complement
+  return (4 * r * (32 / R) >= 32) ? tw_cos(r * (32 / R) - 8, 32) : tw_cos(8 - r * (32 / R), 32);
+}
+
+// v[r] *= exp(-+ 2 pi i r / R) for a compile-time r (exact for r = 0 and r = R / 4)
+template <int R, int r, bool INV, typename T>
+__device__ __forceinline__ cx<T> twiddle_const(cx<T> a) {
+  if constexpr (r == 0) {
+    return a;
+  } else if constexpr (4 * r == R) {
+    return mul_mi<INV>(a);
+  } else {
+    constexpr T c = T(tw_cos(r, R)), sn = T(-tw_sin(r, R));
+    return mul_const<INV>(a, c, sn);
+  }
+}
+
+template <int R, bool INV, typename T, int r = 0>
+__device__ __forceinline__ void twiddle_all(cx<T>* b) {
+  if constexpr (r < R / 2) {
+    b[r] = twiddle_const<R, r, INV>(b[r]);
+    twiddle_all<R, INV, T, r + 1>(b);
+  }
+}
+
+// Length-R DFT of inputs whose upper half is zero (v[r], r >= R / 2, unread):
+// output 2 m takes DFT_{R/2}(v[r]), output 2 m + 1 takes DFT_{R/2}(v[r] w_R^r).
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void dft_half_in(cx<T>* v) {
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    v[1] = v[0];
+  } else {
+    cx<T> a[R / 2], b[R / 2];
+#pragma unroll
+    for (int r = 0; r < R / 2; ++r) a[r] = b[r] = v[r];
+    twiddle_all<R, INV>(b);
+    Dft<R / 2, INV, T>::run(a);
+    Dft<R / 2, INV, T>::run(b);
+#pragma unroll
+    for (int m = 0; m < R / 2; ++m) {
+      v[2 * m] = a[m];
+      v[2 * m + 1] = b[m];
+    }
+  }
+}
+
+// Outputs m < R / 2 of a length-R DFT (the others are not computed):
+// s[r] = v[r] + v[r + R/2] gives the even outputs, d[r] = (v[r] - v[r + R/2]) w_R^r
+// the odd ones, each the first half of a length-R/2 DFT.
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void dft_half_out(cx<T>* v) {
+  if constexpr (R == 2) {
+    v[0] = cadd(v[0], v[1]);
+  } else if constexpr (R == 3 || R == 1) {
+    Dft<R, INV, T>::run(v);
+  } else {
+    cx<T> s[R / 2], d[R / 2];
+#pragma unroll
+    for (int r = 0; r < R / 2; ++r) {
+      s[r] = cadd(v[r], v[r + R / 2]);
+      d[r] = csub(v[r], v[r + R / 2]);
+    }
+    twiddle_all<R, INV>(d);
+    dft_half_out<R / 2, INV, T>(s);
+    dft_half_out<R / 2, INV, T>(d);
+#pragma unroll
+    for (int m = 0; m < R / 4; ++m) {
+      v[2 * m] = s[m];
+      v[2 * m + 1] = d[m];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- barriers
 // Workgroup barrier for LDS reuse only: waits for this wave's LDS traffic,
 // then synchronises the waves.  Global loads and stores stay in flight (the
@@ -456,7 +555,9 @@ __device__ __forceinline__ void lds_stages(cx<T>* lds, const cx<T>* __restrict__
 }
 
 // Last stage: inputs from LDS, outputs left in registers v[j][m] = row b + m L/R.
-template <typename T, int L, int PID, bool REV, int NQ, bool INV, bool FULL = false, int J, int R, class IDX>
+// HALF: only the outputs m < R / 2 are computed (the rest are left undefined).
+template <typename T, int L, int PID, bool REV, int NQ, bool INV, bool FULL = false, bool HALF = false, int J, int R,
+          class IDX>
 __device__ __forceinline__ void lds_last_stage(const cx<T>* lds, const cx<T>* __restrict__ tw, int q,
                                                IDX idx, cx<T> (&v)[J][R]) {
   constexpr int S = plan_len(L, PID) - 1;
@@ -472,7 +573,10 @@ __device__ __forceinline__ void lds_last_stage(const cx<T>* lds, const cx<T>* __
 #pragma unroll
       for (int r = 0; r < R; ++r) v[j][r] = lds[idx(b + r * NB)];
       stage_twiddles<T, L, PID, REV, S, INV, FULL>(v[j], tw, b);
-      Dft<R, INV, T>::run(v[j]);
+      if constexpr (HALF)
+        dft_half_out<R, INV, T>(v[j]);
+      else
+        Dft<R, INV, T>::run(v[j]);
     }
   }
 }

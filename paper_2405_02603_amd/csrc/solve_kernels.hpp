@@ -127,7 +127,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
   place_column<TC>(a, c, col, outer, cok);
   cx<T>* base = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)outer * a.outer_stride + col;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
-  const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
+  const unsigned rs = (unsigned)a.row_stride;  // row offsets of one pencil fit in 32 bits (unsigned: no sign extension)
   auto idx = [c](int row) { return row * TC + c; };
   constexpr bool REV = INV;
   using F = FirstStage<L, PID, REV, NQ>;
@@ -144,7 +144,14 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
       const bool pad = !INV && r >= F::R / 2;
       v[j][r] = (ok && !pad) ? base[(b + r * F::NB) * rs] : czero<T>();
     }
-    Dft<F::R, INV, T>::run(v[j]);
+    // forward: upper half of the inputs is zero; inverse with one stage: only
+    // the lower half of the outputs is kept
+    if constexpr (INV && K == 1)
+      dft_half_out<F::R, true, T>(v[j]);
+    else if constexpr (INV)
+      Dft<F::R, true, T>::run(v[j]);
+    else
+      dft_half_in<F::R, false, T>(v[j]);
   }
   if constexpr (K == 1) {
 #pragma unroll
@@ -163,7 +170,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
     using Ls = LastStage<L, PID, REV, NQ>;
     static_assert(!INV || Ls::R % 2 == 0, "inverse plans end with an even radix");
     cx<T> w[Ls::J][Ls::R];
-    lds_last_stage<T, L, PID, REV, NQ, INV>(lds, tw, q, idx, w);
+    lds_last_stage<T, L, PID, REV, NQ, INV, false, INV>(lds, tw, q, idx, w);
 #pragma unroll
     for (int j = 0; j < Ls::J; ++j) {
       const int b = q + NQ * j;
@@ -222,7 +229,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
     cok = col < a.ncols;
   }
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
-  const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
+  const unsigned rs = (unsigned)a.row_stride;  // row offsets of one pencil fit in 32 bits (unsigned: no sign extension)
   auto idx = [c](int row) { return row * TC + c; };
   using F = FirstStage<L, PID, false, NQ>;   // forward, first stage
   using Lf = LastStage<L, PID, false, NQ>;   // forward, last stage == inverse, first stage
@@ -246,12 +253,16 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   // the octant is stored in column tiles of TC, so a tile's rows are contiguous.
   // GRAD: the table of output o is a.oghat[o], in the same layout.
   const long long goff = (long long)p * a.g_k1_stride + (long long)(col / TC) * (L / 2 + 1) * TC + (col % TC);
+  // Every lane's address lies inside the table (a lane past the last column
+  // reads the zero-filled slots of the last column tile, and a gathered lane
+  // past n1 reads row 0), so the loads need no predicate; those lanes' results
+  // are never stored.
   auto load_g = [&](const void* table, T (&gv)[Lf::J][Lf::R]) {
     const T* g = reinterpret_cast<const T*>(table) + goff;
 #pragma unroll
     for (int j = 0; j < Lf::J; ++j) {
       const int b = q + NQ * j;
-      const bool ok = cok && ((Lf::NB % NQ == 0) || b < Lf::NB);
+      const bool ok = (Lf::NB % NQ == 0) || b < Lf::NB;
 #pragma unroll
       for (int m = 0; m < Lf::R; ++m) {
         const int k0 = b + m * Lf::NB;
@@ -295,7 +306,11 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       const int b = q + NQ * j;
       const bool ok = on && cok && ((F::NB % NQ == 0) || b < F::NB);
 #pragma unroll
-      for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ok ? ld_once(&base[(b + r * F::NB) * rs]) : czero<T>();
+      for (int r = 0; r < F::R / 2; ++r) raw[j][r] = czero<T>();
+      if (ok) {  // one branch around the butterfly's loads
+#pragma unroll
+        for (int r = 0; r < F::R / 2; ++r) raw[j][r] = ld_once(&base[(b + r * F::NB) * rs]);
+      }
     }
   };
   const cx<T>* tws = TWF ? static_cast<const cx<T>*>(twl) : tw;
@@ -312,7 +327,11 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
         x[j][m] = w[j][m];
         multiply(x[j][m], gt[j][m], comp, b + m * Lf::NB, upper_k1);
       }
-      Dft<Lf::R, true, T>::run(x[j]);  // K == 1: the whole inverse; else its first stage (span 1)
+      // K == 1: the whole inverse, of which only the lower half is kept; else its first stage (span 1)
+      if constexpr (K == 1)
+        dft_half_out<Lf::R, true, T>(x[j]);
+      else
+        Dft<Lf::R, true, T>::run(x[j]);
     }
     if constexpr (K == 1) {
 #pragma unroll
@@ -329,7 +348,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       lds_barrier();
       lds_stages<T, L, PID, true, 1, K - 1, NQ, true, TWF>(lds, tws, q, idx);
       cx<T> u[Li::J][Li::R];
-      lds_last_stage<T, L, PID, true, NQ, true, TWF>(lds, tws, q, idx, u);
+      lds_last_stage<T, L, PID, true, NQ, true, TWF, true>(lds, tws, q, idx, u);
 #pragma unroll
       for (int j = 0; j < Li::J; ++j) {
         const int b = q + NQ * j;
@@ -348,8 +367,8 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
 #pragma unroll
     for (int j = 0; j < F::J; ++j) {
 #pragma unroll
-      for (int r = 0; r < F::R; ++r) v[j][r] = r < F::R / 2 ? raw[j][r] : czero<T>();
-      Dft<F::R, false, T>::run(v[j]);
+      for (int r = 0; r < F::R / 2; ++r) v[j][r] = raw[j][r];
+      dft_half_in<F::R, false, T>(v[j]);  // the upper half is the zero padding
     }
     cx<T> w[Lf::J][Lf::R];
     if constexpr (K == 1) {
@@ -435,7 +454,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv_pipe(ColArgs a) {
   const int tid = threadIdx.x;
   const int c = tid % TC, q = tid / TC;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
-  const int rs = (int)a.row_stride;  // row offsets of one pencil fit in 32 bits
+  const unsigned rs = (unsigned)a.row_stride;  // row offsets of one pencil fit in 32 bits (unsigned: no sign extension)
   auto idx = [c](int row) { return row * TC + c; };
   using F = FirstStage<L, PID, false, NQ>;
   using Lf = LastStage<L, PID, false, NQ>;
@@ -475,8 +494,8 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv_pipe(ColArgs a) {
 #pragma unroll
     for (int j = 0; j < F::J; ++j) {
 #pragma unroll
-      for (int r = 0; r < F::R; ++r) v[j][r] = r < F::R / 2 ? raw[j][r] : czero<T>();
-      Dft<F::R, false, T>::run(v[j]);
+      for (int r = 0; r < F::R / 2; ++r) v[j][r] = raw[j][r];
+      dft_half_in<F::R, false, T>(v[j]);  // the upper half is the zero padding
     }
     write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
     lds_barrier();
@@ -500,7 +519,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv_pipe(ColArgs a) {
     lds_barrier();
     lds_stages<T, L, PID, true, 1, K - 1, NQ, true>(lds, tw, q, idx);
     cx<T> u[Li::J][Li::R];
-    lds_last_stage<T, L, PID, true, NQ, true>(lds, tw, q, idx, u);
+    lds_last_stage<T, L, PID, true, NQ, true, false, true>(lds, tw, q, idx, u);
 #pragma unroll
     for (int j = 0; j < Li::J; ++j) {
       const int b = q + NQ * j;
@@ -657,7 +676,7 @@ __global__ __launch_bounds__(NT) void k_slab_conv(SlabArgs a) {
 #pragma unroll
         for (int r = 0; r < F::R; ++r)
           v[j][r] = (ok && r < F::R / 2) ? lds[(b + r * F::NB) * L1 * TC + k1 * TC + c] : czero<T>();
-        Dft<F::R, false, T>::run(v[j]);
+        dft_half_in<F::R, false, T>(v[j]);
       }
       if constexpr (K == 1) {
         const int k1f = k1 <= N1 ? k1 : L1 - k1;
@@ -672,7 +691,7 @@ __global__ __launch_bounds__(NT) void k_slab_conv(SlabArgs a) {
             const int kf = k0 <= N0 ? k0 : L0 - k0;
             v[j][m] = cscale(v[j][m], ok ? g[kf * a.gt] : T(0));
           }
-          Dft<F::R, true, T>::run(v[j]);
+          dft_half_out<F::R, true, T>(v[j]);  // rows >= N0 are dropped
         }
         lds_barrier();
 #pragma unroll
@@ -696,7 +715,7 @@ __global__ __launch_bounds__(NT) void k_slab_conv(SlabArgs a) {
 #pragma unroll
           for (int r = 0; r < F2::R; ++r)
             v2[j][r] = (ok && r < F2::R / 2) ? lds[(b + r * F2::NB) * L1 * TC + k1 * TC + c] : czero<T>();
-          Dft<F2::R, false, T>::run(v2[j]);
+          dft_half_in<F2::R, false, T>(v2[j]);
         }
         write_first_outputs<T, F2::R, F2::J, F2::NB, NQ0>(pen, v2, q, pidx);
         lds_barrier();
@@ -722,7 +741,7 @@ __global__ __launch_bounds__(NT) void k_slab_conv(SlabArgs a) {
         lds_barrier();
         lds_stages<T, L0, PID0, true, 1, K - 1, NQ0, true>(pen, tw0, q, pidx);
         cx<T> u[Li::J][Li::R];
-        lds_last_stage<T, L0, PID0, true, NQ0, true>(pen, tw0, q, pidx, u);
+        lds_last_stage<T, L0, PID0, true, NQ0, true, false, true>(pen, tw0, q, pidx, u);
         // back into the slab, rows < N0 (all of this group's reads of the slab are done)
 #pragma unroll
         for (int j = 0; j < Li::J; ++j) {
@@ -790,8 +809,8 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
 #pragma unroll
     for (int j = 0; j < F::J; ++j) {
 #pragma unroll
-      for (int r = 0; r < F::R; ++r) v[j][r] = r < F::R / 2 ? raw[g][j][r] : czero<T>();
-      Dft<F::R, false, T>::run(v[j]);
+      for (int r = 0; r < F::R / 2; ++r) v[j][r] = raw[g][j][r];
+      dft_half_in<F::R, false, T>(v[j]);  // the upper half of z is the zero padding
     }
     if constexpr (K == 1) {
       write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
@@ -891,7 +910,10 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
           const cx<T> B = cmulc(csub(X1, X2), pp[n]);
           v[j][r] = {A.x - B.y, A.y + B.x};
         }
-        Dft<F::R, true, T>::run(v[j]);
+        if constexpr (K == 1)
+          dft_half_out<F::R, true, T>(v[j]);  // only the first half of z is kept
+        else
+          Dft<F::R, true, T>::run(v[j]);
       }
     }
     cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)row * (LC / 2);
@@ -915,7 +937,7 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
       using Li = LastStage<LC, PID, true, NQ>;
       static_assert(Li::R % 2 == 0, "inverse plans end with an even radix");
       cx<T> u[Li::J][Li::R];
-      lds_last_stage<T, LC, PID, true, NQ, true>(lds, tw, q, idx, u);
+      lds_last_stage<T, LC, PID, true, NQ, true, false, true>(lds, tw, q, idx, u);
       if (rok) {
 #pragma unroll
         for (int j = 0; j < Li::J; ++j) {
