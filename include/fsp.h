@@ -232,18 +232,27 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
 fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const* rho,
                              void* const* phi, void* stream);
 
-/* A fixed set of solves replayed as one HIP graph (no per-call launch cost;
- * no passage of the paper: a launch-cost device of this library).
+/* A set of solves replayed as one HIP graph (no per-call launch cost; no
+ * passage of the paper: a launch-cost device of this library).
  * fsp_batch_create records count (plan, rho, phi) triples with the rules of
- * fsp_solve_batched; nothing is enqueued.  The plans, their bound buffers and
- * the rho/phi arrays must stay alive and unchanged (no re-bind, no
- * re-precompute into other buffers) while the batch exists.  The first
- * fsp_batch_launch captures the grouped launches of all solves into a graph
- * (equal shapes share launches; launch groups become parallel branches) and
- * launches it on `stream`; later calls replay the same graph.  Concurrent
- * launches of one batch race on its workspaces. */
+ * fsp_solve_batched and writes their buffers into a device-resident table (one
+ * device allocation, owned by the batch); nothing is enqueued.  Solves of equal
+ * shape form one launch group, however many there are (up to 65535 per
+ * group), and the groups become parallel branches of the graph.  The first
+ * fsp_batch_launch captures the launches, which read every item's buffers from
+ * the table when they run, and launches the graph on `stream`; later calls
+ * replay it.  fsp_batch_set_io(b, rho, phi, stream) replaces the rho / phi of
+ * every solve (count entries each, in the order of fsp_batch_create): one
+ * small kernel per 64 solves writes them into the table on `stream`, so a
+ * later launch on that stream (or one ordered after it) uses them with no new
+ * capture; launches already enqueued before it use the old ones.  The plans
+ * and their bound buffers must stay alive and unchanged (no re-bind) while the
+ * batch exists; rho / phi must stay alive while a launch that uses them runs.
+ * Concurrent launches of one batch race on its workspaces.
+ * FSP_ERR_OUT_OF_MEMORY if the table cannot be allocated. */
 fsp_status fsp_batch_create(int count, const fsp_plan* plans, const void* const* rho, void* const* phi,
                             fsp_batch* out);
+fsp_status fsp_batch_set_io(fsp_batch b, const void* const* rho, void* const* phi, void* stream);
 fsp_status fsp_batch_launch(fsp_batch b, void* stream);
 fsp_status fsp_batch_destroy(fsp_batch b);
 

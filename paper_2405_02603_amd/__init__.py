@@ -311,10 +311,12 @@ def solve_batched(plans: Sequence[Plan], rhos: Sequence, outs: Optional[Sequence
 
 
 class Batch:
-    """A fixed set of solves replayed as one captured HIP graph (fsp_batch_*).
+    """A set of solves replayed as one captured HIP graph (fsp_batch_*).
 
-    The plans, rho and out tensors are held for the batch's lifetime; the first
-    launch captures the graph, later launches replay it.
+    The plans and the current rho / out tensors are held by the batch; the first
+    launch captures the graph, later launches replay it.  ``set_io`` swaps in new
+    rho / out tensors (the kernels read them from a device table), with no new
+    capture.
     """
 
     def __init__(self, plans: Sequence[Plan], rhos: Sequence, outs: Optional[Sequence] = None):
@@ -337,6 +339,27 @@ class Batch:
         h = ctypes.c_void_p()
         check(self._lib.fsp_batch_create(count, hp, rp, op, ctypes.byref(h)), "fsp_batch_create")
         self._h = h
+
+    def set_io(self, rhos: Sequence, outs: Optional[Sequence] = None, stream=None):
+        """New rho (and out) tensors for every solve, in the batch's order (fsp_batch_set_io);
+        launches enqueued after this on the same stream use them."""
+        torch = _torch()
+        if len(rhos) != len(self.plans):
+            raise ValueError("need one rho per solve")
+        if outs is None:
+            outs = [torch.empty_like(r) for r in rhos]
+        if len(outs) != len(self.plans):
+            raise ValueError("need one output per solve")
+        for p, r, o in zip(self.plans, rhos, outs):
+            p._check_field(r, "rho")
+            p._check_field(o, "out")
+        arr = ctypes.c_void_p * len(self.plans)
+        rp = arr(*[r.data_ptr() for r in rhos])
+        op = arr(*[o.data_ptr() for o in outs])
+        with torch.cuda.device(self.device):
+            check(self._lib.fsp_batch_set_io(self._h, rp, op, _stream_ptr(stream)), "fsp_batch_set_io")
+        self.rhos, self.outs = list(rhos), list(outs)
+        return self.outs
 
     def launch(self, stream=None):
         torch = _torch()

@@ -31,7 +31,7 @@ EXPORTS = (
     "fsp_plan_create", "fsp_plan_bytes", "fsp_plan_precompute_bytes", "fsp_plan_bind",
     "fsp_plan_share_ghat", "fsp_precompute", "fsp_solve", "fsp_solve_passes", "fsp_solve_batched", "fsp_plan_destroy",
     "fsp_plan_ghat_layout", "fsp_plan_model_bytes", "fsp_status_str", "fsp_last_error", "fsp_version",
-    "fsp_batch_create", "fsp_batch_launch", "fsp_batch_destroy",
+    "fsp_batch_create", "fsp_batch_launch", "fsp_batch_destroy", "fsp_batch_set_io",
     "fsp_plan_get_schedule", "fsp_plan_set_schedule", "fsp_autotune",
     "fsp_solve_grad", "fsp_plan_octant_offset", "fsp_solve_static",
 )
@@ -91,6 +91,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "fsp_batch_create": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                      POINTER(c_void_p)]),
         "fsp_batch_launch": (c_int, [P, P]),
+        "fsp_batch_set_io": (c_int, [P, POINTER(c_void_p), POINTER(c_void_p), P]),
         "fsp_plan_get_schedule": (c_int, [P, POINTER(c_int)]),
         "fsp_plan_set_schedule": (c_int, [P, POINTER(c_int)]),
         "fsp_autotune": (c_int, [P, P, P, c_int, P, POINTER(ctypes.c_float)]),

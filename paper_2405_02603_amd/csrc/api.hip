@@ -1165,18 +1165,48 @@ fsp_status fsp_plan_destroy(fsp_plan p) {
 
 struct fsp_batch_s {
   std::vector<fsp_plan> plans;
-  std::vector<const void*> rho;
-  std::vector<void*> phi;
+  std::vector<int> slot;            // table slot of solve i
+  // launch groups: equal shapes, contiguous table slots [first, first + count)
+  struct Group {
+    int first, count;
+    fsp_plan plan;                  // a member (the group's shape and schedule)
+  };
+  std::vector<Group> groups;
+  std::vector<fsp::ItemPtrs> host;  // the table as last written (slot order)
+  fsp::ItemPtrs* table = nullptr;   // the device table the captured kernels read
   int device = 0;
-  int branches = 4;
+  // graph branches the launch groups are spread over: one (groups in turn,
+  // largest first) measured fastest on the 64-solve mix -- concurrent groups
+  // slow each other's kernels more than they fill idle compute units
+  int branches = 1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
-// Capture the grouped launches of a batch as one graph whose launch groups run
-// on parallel branches.
+// New inputs and outputs of up to SET_ITEMS table slots, written by one launch
+// (the values travel in the kernel arguments, so the update is ordered on the
+// caller's stream like any kernel and needs no host staging buffer).
+constexpr int SET_ITEMS = 64;
+struct SetItemsArgs {
+  fsp::ItemPtrs* table;
+  int count;
+  int slot[SET_ITEMS];
+  const void* rho[SET_ITEMS];
+  void* phi[SET_ITEMS];
+};
+
+__global__ __launch_bounds__(SET_ITEMS) void k_set_items(SetItemsArgs a) {
+  const int i = threadIdx.x;
+  if (i < a.count) {
+    a.table[a.slot[i]].rho = a.rho[i];
+    a.table[a.slot[i]].phi = a.phi[i];
+  }
+}
+
+// Capture the group launches of a batch as one graph whose launch groups run
+// on parallel branches; every launch reads its items' buffers from the table.
 hipError_t capture_batch(fsp_batch_s* b) {
   const int nb = b->branches;
   hipStream_t cs = nullptr;
@@ -1194,9 +1224,12 @@ hipError_t capture_batch(fsp_batch_s* b) {
   }
   if (e == hipSuccess) e = hipEventRecord(fork, cs);
   for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[i], fork, 0);
-  if (e == hipSuccess) {
-    fsp_status st = enqueue_batch((int)b->plans.size(), b->plans.data(), b->rho.data(), b->phi.data(), side.data(), nb);
-    if (st != FSP_OK) e = hipErrorLaunchFailure;
+  for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
+    const fsp_batch_s::Group& gr = b->groups[k];
+    fsp::SolveGeom g = group_geom(gr.plan);
+    g.items = gr.count;
+    g.items_dev = b->table + gr.first;
+    e = run_group(g, gr.plan->d.prec == FSP_F64, 0, 4, side[k % nb]);
   }
   for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipEventRecord(join[i], side[i]);
   for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(cs, join[i], 0);
@@ -1220,6 +1253,13 @@ hipError_t capture_batch(fsp_batch_s* b) {
   return e;
 }
 
+void free_batch(fsp_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->table) (void)hipFree(b->table);
+  delete b;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1234,10 +1274,86 @@ fsp_status fsp_batch_create(int count, const fsp_plan* plans, const void* const*
   fsp_batch_s* b = new (std::nothrow) fsp_batch_s();
   if (!b) return fail(FSP_ERR_OUT_OF_MEMORY, "fsp_batch_create: host allocation failed");
   b->plans.assign(plans, plans + count);
-  b->rho.assign(rho, rho + count);
-  b->phi.assign(phi, phi + count);
   b->device = plans[0]->device;
+  b->slot.assign(count, -1);
+  // one launch group per shape, its items in consecutive table slots
+  for (int i = 0; i < count; ++i) {
+    if (b->slot[i] >= 0) continue;
+    fsp_batch_s::Group gr{(int)b->host.size(), 0, plans[i]};
+    for (int j = i; j < count; ++j) {
+      if (b->slot[j] >= 0 || !same_shape(plans[i], plans[j])) continue;
+      if (gr.count == 65535) break;  // the launch grid's item axis
+      b->slot[j] = (int)b->host.size();
+      fsp::ItemPtrs it;
+      it.rho = rho[j];
+      it.phi = phi[j];
+      it.work = plans[j]->work;
+      it.ghat = static_cast<const char*>(plans[j]->ghat_read) + plans[j]->oct_off;
+      b->host.push_back(it);
+      ++gr.count;
+    }
+    b->groups.push_back(gr);
+  }
+  for (int i = 0; i < count; ++i)
+    if (b->slot[i] < 0) {  // a shape with more than 65535 solves: its own groups
+      fsp_batch_s::Group gr{(int)b->host.size(), 0, plans[i]};
+      for (int j = i; j < count && gr.count < 65535; ++j) {
+        if (b->slot[j] >= 0 || !same_shape(plans[i], plans[j])) continue;
+        b->slot[j] = (int)b->host.size();
+        b->host.push_back(fsp::ItemPtrs{rho[j], phi[j], plans[j]->work,
+                                        static_cast<const char*>(plans[j]->ghat_read) + plans[j]->oct_off});
+        ++gr.count;
+      }
+      b->groups.push_back(gr);
+    }
+  // the group that moves the most bytes starts first, on the first branch
+  std::stable_sort(b->groups.begin(), b->groups.end(), [](const fsp_batch_s::Group& x, const fsp_batch_s::Group& y) {
+    return model_bytes(x.plan) * x.count > model_bytes(y.plan) * y.count;
+  });
+  if (const char* env = std::getenv("FSP_BATCH_BRANCHES")) b->branches = std::max(1, std::min(16, std::atoi(env)));
+  DeviceGuard guard;
+  hipError_t e = guard.enter(b->device);
+  if (e == hipSuccess) e = hipMalloc(&b->table, b->host.size() * sizeof(fsp::ItemPtrs));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b->table = nullptr;
+    free_batch(b);
+    return fail(FSP_ERR_OUT_OF_MEMORY, "fsp_batch_create: device table allocation failed");
+  }
+  e = hipMemcpy(b->table, b->host.data(), b->host.size() * sizeof(fsp::ItemPtrs), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return fail_hip(e, "fsp_batch_create: table upload");
+  }
   *out = b;
+  return FSP_OK;
+}
+
+fsp_status fsp_batch_set_io(fsp_batch b, const void* const* rho, void* const* phi, void* stream) {
+  if (!b || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, "fsp_batch_set_io: NULL argument");
+  const int count = (int)b->plans.size();
+  for (int i = 0; i < count; ++i)
+    if (!rho[i] || !phi[i]) return fail(FSP_ERR_INVALID_ARG, "fsp_batch_set_io: NULL entry " + std::to_string(i));
+  DeviceGuard guard;
+  hipError_t e = guard.enter(b->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_batch_set_io: hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  for (int i0 = 0; i0 < count && e == hipSuccess; i0 += SET_ITEMS) {
+    SetItemsArgs a{};
+    a.table = b->table;
+    a.count = std::min(SET_ITEMS, count - i0);
+    for (int k = 0; k < a.count; ++k) {
+      const int i = i0 + k;
+      a.slot[k] = b->slot[i];
+      a.rho[k] = rho[i];
+      a.phi[k] = phi[i];
+      b->host[b->slot[i]].rho = rho[i];
+      b->host[b->slot[i]].phi = phi[i];
+    }
+    hipLaunchKernelGGL(k_set_items, dim3(1), dim3(SET_ITEMS), 0, s, a);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return fail_hip(e, "fsp_batch_set_io");
   return FSP_OK;
 }
 
@@ -1259,9 +1375,7 @@ fsp_status fsp_batch_destroy(fsp_batch b) {
   if (!b) return fail(FSP_ERR_INVALID_ARG, "fsp_batch_destroy: NULL batch");
   DeviceGuard guard;
   (void)guard.enter(b->device);
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  delete b;
+  free_batch(b);
   return FSP_OK;
 }
 

@@ -37,7 +37,20 @@ namespace fsp {
 constexpr int MAX_ITEMS = 16;
 constexpr int MAX_OUT = 4;  // outputs of the gradient solve's axis-0 pass: three components and phi
 
+// Buffers of one solve in a device-resident table.  A launch with a table
+// (ColArgs/RowArgs/SlabArgs::items != NULL) reads item blockIdx.y's pointers
+// from it when it runs, not from its arguments: a captured graph of such
+// launches takes new rho / phi from an updated table without being captured
+// again, and a launch may hold any number of items.
+struct ItemPtrs {
+  const void* rho;
+  void* phi;
+  void* work;        // S
+  const void* ghat;  // the Green's octant, blocked as ColArgs::ghat
+};
+
 struct ColArgs {
+  const ItemPtrs* items;      // table of this launch's items, or NULL (then data / ghat)
   void* data[MAX_ITEMS];      // S of each item
   const void* ghat[MAX_ITEMS];  // P3: Green's octant of each item, blocked [n1+1][tiles][n0+1][TC]
   const void* tw;             // twiddle table of this pencil length
@@ -59,6 +72,7 @@ struct ColArgs {
 };
 
 struct RowArgs {
+  const ItemPtrs* items;      // table of this launch's items, or NULL (then in / out)
   const void* in[MAX_ITEMS];
   void* out[MAX_ITEMS];
   const void* tw;             // twiddles of length n2, then exp(-i pi k / n2), k in [0, n2]
@@ -70,6 +84,14 @@ struct RowArgs {
 
 template <typename T>
 __device__ __forceinline__ cx<T> czero() { return {T(0), T(0)}; }
+
+// The buffers of this block's item (blockIdx.y): from the launch's table, else its arguments.
+template <class A>
+__device__ __forceinline__ void* item_work(const A& a) { return a.items ? a.items[blockIdx.y].work : a.data[blockIdx.y]; }
+template <class A>
+__device__ __forceinline__ const void* item_ghat(const A& a) {
+  return a.items ? a.items[blockIdx.y].ghat : a.ghat[blockIdx.y];
+}
 
 // Load of a value that this launch reads exactly once (streamed, non-temporal).
 template <typename T>
@@ -125,7 +147,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
   int col, outer;
   bool cok;
   place_column<TC>(a, c, col, outer, cok);
-  cx<T>* base = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]) + (long long)outer * a.outer_stride + col;
+  cx<T>* base = reinterpret_cast<cx<T>*>(item_work(a)) + (long long)outer * a.outer_stride + col;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   const unsigned rs = (unsigned)a.row_stride;  // row offsets of one pencil fit in 32 bits (unsigned: no sign extension)
   auto idx = [c](int row) { return row * TC + c; };
@@ -272,7 +294,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
     }
   };
   T gv[Lf::J][Lf::R];
-  load_g(GRAD ? a.oghat[0] : a.ghat[blockIdx.y], gv);
+  load_g(GRAD ? a.oghat[0] : item_ghat(a), gv);
   // GRAD with registers to spare: the next output's table values are loaded
   // while the current output is transformed
   constexpr bool GPRE = NOUT > 1 && sizeof(T) * L / NQ <= 64;
@@ -287,7 +309,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   const bool two = cok && paired;
   const long long off_a = (long long)p * a.outer_stride + col;
   const long long off_b = (long long)(2 * a.n1 - p) * a.outer_stride + col;
-  cx<T>* const data = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]);
+  cx<T>* const data = reinterpret_cast<cx<T>*>(item_work(a));
   // The derivative tables are odd along their axis: their transform is -i T with
   // the real octant T read at the folded frequency and negated on the upper half
   // of that axis (k0 > n0; for axis 1 the partner 2 n1 - p; axis 2 holds k2 <= n2).
@@ -461,8 +483,8 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv_pipe(ColArgs a) {
   using Li = LastStage<L, PID, true, NQ>;
   static_assert(F::R % 2 == 0 && Li::R % 2 == 0, "plans start with an even radix");
   const int nitems = a.nouter * a.ntiles;
-  cx<T>* data = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]);
-  const T* ghat = reinterpret_cast<const T*>(a.ghat[blockIdx.y]);
+  cx<T>* data = reinterpret_cast<cx<T>*>(item_work(a));
+  const T* ghat = reinterpret_cast<const T*>(item_ghat(a));
 
   // pencil set (item w, which) of this thread: its column base and Green's rows
   auto set_base = [&](int w, int which) -> cx<T>* {
@@ -610,6 +632,7 @@ __device__ __forceinline__ void slab_fft(cx<T>* lds, const cx<T>* __restrict__ t
 // N0 = L0 / 2, N1 = L1 / 2.  tw1: twiddles of length L1 (plan PID1), tw0: of
 // length L0 (plan PID0); ghat blocked in column tiles of GT.
 struct SlabArgs {
+  const ItemPtrs* items;      // table of this launch's items, or NULL (then data / ghat)
   void* data[MAX_ITEMS];
   const void* ghat[MAX_ITEMS];
   const void* tw1;
@@ -628,8 +651,8 @@ __global__ __launch_bounds__(NT) void k_slab_conv(SlabArgs a) {
   __shared__ cx<T> lds[N0 * L1 * TC];
   const int tid = threadIdx.x;
   const int col0 = blockIdx.x * TC;
-  cx<T>* S = reinterpret_cast<cx<T>*>(a.data[blockIdx.y]);
-  const T* ghat = reinterpret_cast<const T*>(a.ghat[blockIdx.y]);
+  cx<T>* S = reinterpret_cast<cx<T>*>(item_work(a));
+  const T* ghat = reinterpret_cast<const T*>(item_ghat(a));
   const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(a.tw1);
   const cx<T>* tw0 = reinterpret_cast<const cx<T>*>(a.tw0);
   // load rows (i0, i1 < N1) of the tile
@@ -788,7 +811,8 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
   for (int g = 0; g < G; ++g) {
     const int row = ((int)blockIdx.x * G + g) * TR + c;
     const bool rok = row < a.nrows;
-    const cx<T>* in = reinterpret_cast<const cx<T>*>(a.in[blockIdx.y]) + (long long)row * (LC / 2);
+    const void* src = a.items ? a.items[blockIdx.y].rho : a.in[blockIdx.y];
+    const cx<T>* in = reinterpret_cast<const cx<T>*>(src) + (long long)row * (LC / 2);
     issue_fence();
 #pragma unroll
     for (int j = 0; j < F::J; ++j) {
@@ -834,7 +858,8 @@ __global__ __launch_bounds__(TR* NQ) void k_row_r2c(RowArgs a) {
     lds_barrier();
     if (rok) {
       const int i0 = row / a.n1, i1 = row - i0 * a.n1;
-      cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
+      void* dst = a.items ? a.items[blockIdx.y].work : a.out[blockIdx.y];
+      cx<T>* out = reinterpret_cast<cx<T>*>(dst) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
       constexpr int JO = (LC + 1 + NQ - 1) / NQ;
 #pragma unroll
       for (int j = 0; j < JO; ++j) {
@@ -873,8 +898,8 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
     const int row = ((int)blockIdx.x * G + g) * TR + c;
     const bool rok = row < a.nrows;
     const int i0 = row / a.n1, i1 = row - i0 * a.n1;
-    const cx<T>* in =
-        reinterpret_cast<const cx<T>*>(a.in[blockIdx.y]) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
+    const void* src = a.items ? a.items[blockIdx.y].work : a.in[blockIdx.y];
+    const cx<T>* in = reinterpret_cast<const cx<T>*>(src) + (long long)i0 * a.s_i0_stride + (long long)i1 * a.pitch;
     issue_fence();
 #pragma unroll
     for (int j = 0; j < JI; ++j) {
@@ -916,7 +941,8 @@ __global__ __launch_bounds__(TR* NQ) void k_row_c2r(RowArgs a) {
           Dft<F::R, true, T>::run(v[j]);
       }
     }
-    cx<T>* out = reinterpret_cast<cx<T>*>(a.out[blockIdx.y]) + (long long)row * (LC / 2);
+    void* dst = a.items ? a.items[blockIdx.y].phi : a.out[blockIdx.y];
+    cx<T>* out = reinterpret_cast<cx<T>*>(dst) + (long long)row * (LC / 2);
     if constexpr (K == 1) {
       static_assert(F::R % 2 == 0, "inverse plans end with an even radix");
       if (rok) {

@@ -313,7 +313,8 @@ extern template hipError_t launch_slab<double>(int, const SlabArgs&, int, hipStr
 
 // Geometry of up to MAX_ITEMS solves of one shape, filled by the plans.
 struct SolveGeom {
-  int items;                 // solves in this group (1 .. MAX_ITEMS)
+  int items;                 // solves in this group (1 .. MAX_ITEMS; up to 65535 with items_dev)
+  const ItemPtrs* items_dev; // device table of the group's buffers (then ghat/work/rho/phi are unused), or NULL
   int n0, n1, n2;
   int pitch;                 // P
   long long plane;           // complex elements between S planes i0 (>= 2 n1 P)
@@ -342,7 +343,13 @@ template <typename T>
 hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) {
   const long long P = g.pitch;
   const long long plane = g.plane;  // complex elements per S plane i0
+  // items from the device table, or up to MAX_ITEMS in the kernel arguments
+  const bool tab = g.items_dev != nullptr;
+  if (!tab && (g.items < 1 || g.items > MAX_ITEMS)) return hipErrorInvalidValue;
+  if (tab && (g.items < 1 || g.items > 65535 || g.nout)) return hipErrorInvalidValue;
+  const int nfill = tab ? 0 : g.items;
   RowArgs ra{};
+  ra.items = g.items_dev;
   ra.nrows = g.n0 * g.n1;
   ra.n1 = g.n1;
   ra.pitch = g.pitch;
@@ -350,7 +357,8 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
 
   // P2 / P4: pencils along axis 1; outer = i0
   ColArgs ca{};
-  for (int i = 0; i < g.items; ++i) ca.data[i] = g.work[i];
+  ca.items = g.items_dev;
+  for (int i = 0; i < nfill; ++i) ca.data[i] = g.work[i];
   ca.ncols = g.n2 + 1;
   ca.row_stride = P;
   ca.outer_stride = plane;
@@ -358,7 +366,8 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
 
   // P3: pencils along axis 0; outer = k1 pairs
   ColArgs cc{};
-  for (int i = 0; i < g.items; ++i) {
+  cc.items = g.items_dev;
+  for (int i = 0; i < nfill; ++i) {
     cc.data[i] = g.work[i];
     cc.ghat[i] = g.ghat[i];
   }
@@ -394,7 +403,7 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
   auto run = [&](int pass, int c0, int c1) -> hipError_t {
     switch (pass) {
       case 0:
-        for (int i = 0; i < g.items; ++i) {
+        for (int i = 0; i < nfill; ++i) {
           ra.in[i] = g.rho[i];
           ra.out[i] = g.work[i];
         }
@@ -421,13 +430,13 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
         return launch_col<T>(2 * g.n0, g.var[2], 2, cc, g.items, s);
       case 3: {
         ColArgs c4 = ca;
-        for (int i = 0; i < npost; ++i) c4.data[i] = after[i];
+        for (int i = 0; i < (tab ? 0 : npost); ++i) c4.data[i] = after[i];
         set_cols(c4, tc4, c0, c1);
         c4.tw = g.tw_c1[3];
         return launch_col<T>(2 * g.n1, g.var[3], 1, c4, npost, s);
       }
       case 4:
-        for (int i = 0; i < npost; ++i) {
+        for (int i = 0; i < (tab ? 0 : npost); ++i) {
           ra.in[i] = after[i];
           ra.out[i] = result[i];
         }
@@ -447,7 +456,8 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
     if (first == 0) e = run(0, 0, ncols);
     if (e != hipSuccess || !mid) return e == hipSuccess && last == 4 ? run(4, 0, ncols) : e;
     SlabArgs sa{};
-    for (int i = 0; i < g.items; ++i) {
+    sa.items = g.items_dev;
+    for (int i = 0; i < nfill; ++i) {
       sa.data[i] = g.work[i];
       sa.ghat[i] = g.ghat[i];
     }

@@ -110,3 +110,42 @@ def test_batched_rejects_shared_workspace(torch_cuda):
     r = torch.zeros((16, 16, 16), device="cuda")
     with pytest.raises(FspError):
         solve_batched([p, p], [r, r])
+
+
+def test_batch_new_inputs_without_capture_and_large_group(torch_cuda):
+    """A captured batch (one launch group per shape, each group any size: here 20 solves of
+    one shape share a launch) takes new inputs through its device table: after set_io the
+    replay solves the new right-hand sides, bit for bit as their solo solves, and every
+    result is the oracle's."""
+    torch = torch_cuda
+    from paper_2405_02603_amd import Batch
+    items = _mix(20, seed=21, sizes=(32,)) + _mix(12, seed=22, sizes=(48, 64, 96, 128))
+    plans, rhos, host = _plans_and_inputs(torch, items, kinds=("vico_dct",))
+    batch = Batch(plans, rhos)
+    batch.launch()
+    torch.cuda.synchronize()
+    for p, r, o in zip(plans, rhos, batch.outs):
+        assert torch.equal(p.solve(r), o)
+    # new sources (each item's own, drawn from another seed), swapped in without a new capture
+    host2 = [W.source_density(it.n, it.lo, it.hi, W.multiblob(seed=500 + i)) for i, it in enumerate(items)]
+    rhos2 = [to_dev(h, torch.float32) for h in host2]
+    for rep in range(2):
+        outs2 = [torch.full_like(r, float("nan")) for r in rhos2]
+        batch.set_io(rhos2, outs2)
+        batch.launch()
+        torch.cuda.synchronize()
+        for p, r, o in zip(plans, rhos2, outs2):
+            assert torch.equal(p.solve(r), o), f"replay {rep}"
+    for i, (it, h, o) in enumerate(zip(items, host2, batch.outs)):
+        ref = reference(h, "vico_dct", it.lo, it.hi, use_direct=False)
+        got = to_host(o)
+        assert rel_l2(got, ref) <= 1e-6, (i, it.n)
+        assert elem_err(got, ref) <= F32_ELEM, (i, it.n)
+    # and back to the first inputs
+    outs1 = [torch.empty_like(r) for r in rhos]
+    batch.set_io(rhos, outs1)
+    batch.launch()
+    torch.cuda.synchronize()
+    for p, r, o in zip(plans, rhos, outs1):
+        assert torch.equal(p.solve(r), o)
+    batch.close()
