@@ -191,8 +191,23 @@ def copy_calibration(torch):
     return {"bytes": 2 * a.numel() * 4, "ms": ms, "GBs": 2 * a.numel() * 4 / ms / 1e6}
 
 
+def cpu_threads():
+    """Host threads for the CPU baseline: every core of this process's affinity set, within the
+    host's CPU share when the environment states one (OMP_NUM_THREADS)."""
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(affinity, int(share)) if share.isdigit() and int(share) > 0 else affinity
+    return max(1, threads), affinity
+
+
 def cpu_baseline(rho64, lo, hi, greens_kind, seconds):
-    """The oracle (float64 FFT route) timed on the host on a bounded sample."""
+    """The oracle (FFT route, scipy) timed on the host on a bounded sample: float64 (the oracle as
+    it stands, about two thirds of the time) and float32 (the same steps in single precision)."""
+    import numpy as np
+
     from oracle import fftroute, greens
 
     n = rho64.shape
@@ -201,26 +216,29 @@ def cpu_baseline(rho64, lo, hi, greens_kind, seconds):
     else:
         k = greens.vico_octant(n, lo, hi)
     h = greens.spacing(n, lo, hi)
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16))
-    ref = None
-    count = 0
-    t0 = time.perf_counter()
-    while True:
-        phi = fftroute.solve(rho64, k, h, workers=cores)
-        if ref is None:
-            ref = phi
-        count += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or count >= 50:
-            break
+    cores, affinity = cpu_threads()
+
+    def leg(dtype, budget_s):
+        ref, count = None, 0
+        t0 = time.perf_counter()
+        while True:
+            phi = fftroute.solve(rho64, k, h, workers=cores, dtype=dtype)
+            if ref is None:
+                ref = phi
+            count += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or count >= 50:
+                return ref, count, el
+
+    ref, count, el = leg(np.float64, seconds * 2.0 / 3.0)
+    ref32, count32, el32 = leg(np.float32, seconds / 3.0)
     out = {"value": count / el, "unit": "solves/s", "cores": cores, "kind": "oracle",
            "sample": f"{count} float64 FFT-route solves of the same {n[0]}^3 workload "
                      f"(scipy.fft, workers={cores}), {el:.1f} s; kernel table excluded",
-           "cpu": cpu_model()}
+           "cpu": cpu_model(), "affinity_cores": affinity,
+           "f32": {"value": count32 / el32, "unit": "solves/s",
+                   "sample": f"{count32} float32 FFT-route solves, {el32:.1f} s",
+                   "rel_l2_vs_f64": float(np.linalg.norm((ref32 - ref).ravel()) / np.linalg.norm(ref.ravel()))}}
     out["direct_sum_32"] = direct_sum_timing()
     return ref, out
 
@@ -316,15 +334,18 @@ def bench_precompute(torch, n, lo, hi):
     return out
 
 
-def bench_batch(args):
-    """64 right-hand sides, n from {32,48,64,96,128} (seed 4), Vico-Greengard float32, one graph launch."""
-    import numpy as np
+def run_batch(args, count=None, steps=None, warmup=None):
+    """64 right-hand sides, n from {32,48,64,96,128} (seed 4), Vico-Greengard float32, one graph
+    launch per step (device table of the items' buffers).  Returns the measurement as a dict."""
     import torch
 
     import workloads as W
     from paper_2405_02603_amd import Batch, Plan
 
-    items = W.batch_mix(seed=4, count=args.batch_count)
+    count = count or args.batch_count
+    steps = steps or args.steps
+    warmup = args.warmup if warmup is None else warmup
+    items = W.batch_mix(seed=4, count=count)
     src = {}
     plans, rhos, host = [], [], []
     tuned = {}
@@ -344,14 +365,14 @@ def bench_batch(args):
         plans.append(p)
         rhos.append(torch.from_numpy(r).to("cuda", torch.float32))
     batch = Batch(plans, rhos)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         batch.launch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         batch.launch()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = (time.perf_counter() - t0) * 1e3 / steps
     model = sum(p.model_bytes for p in plans)
     # the same right-hand sides as plain float64 single solves, one at a time
     p64 = {}
@@ -362,7 +383,7 @@ def bench_batch(args):
     outs64 = [p64[it.n].solve(r) for it, r in zip(items, r64)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    reps = max(1, args.steps // 4)
+    reps = max(1, steps // 4)
     for _ in range(reps):
         for it, r, o in zip(items, r64, outs64):
             p64[it.n].solve(r, o)
@@ -371,69 +392,85 @@ def bench_batch(args):
     err = max(float(torch.linalg.vector_norm((o32.double() - o64).flatten()) / torch.linalg.vector_norm(o64.flatten()))
               for o32, o64 in zip(batch.outs, outs64))
     sizes = sorted({it.n for it in items})
+    out = {"solves_per_s": round(len(items) * 1e3 / ms, 1), "ms_per_step": round(ms, 4), "count": len(items),
+           "sizes": sizes, "steps": steps, "hbm_frac_model": round(model / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+           "model_bytes_per_step": model,
+           "fp64_single_solves": {"solves_per_s": round(len(items) * 1e3 / ms64, 1), "ms_per_batch": round(ms64, 4)},
+           "max_rel_l2_f32_vs_gpu_f64": err,
+           "schedules": {str(k): v for k, v in sorted(tuned.items())}}
+    batch.close()
+    return out
+
+
+def bench_batch(args):
+    r = run_batch(args)
     out = {
         "metric": "batched Vico-Greengard solves/s (64 uneven right-hand sides per graph launch)",
-        "value": round(len(items) * 1e3 / ms, 1), "unit": "solves/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "value": r["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{len(items)} right-hand sides, n in {sizes} (seed 4), [-1,1]^3, 8 Gaussians each, "
-                               "vico_dct float32, one captured graph per step"},
-        "hbm_frac_model": round(model / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
-        "model_bytes_per_step": model,
-        "fp64_single_solves": {"solves_per_s": round(len(items) * 1e3 / ms64, 1), "ms_per_batch": round(ms64, 4)},
-        "max_rel_l2_f32_vs_gpu_f64": err,
-        "schedules": {str(k): v for k, v in sorted(tuned.items())},
+        "config": {"workload": f"{r['count']} right-hand sides, n in {r['sizes']} (seed 4), [-1,1]^3, 8 Gaussians "
+                               "each, vico_dct float32, one captured graph per step"},
     }
+    out.update({k: v for k, v in r.items() if k not in ("solves_per_s", "ms_per_step")})
     print(json.dumps(out), flush=True)
     return 0
 
 
-def bench_serve(args):
-    """Poisson arrivals, n in {32..256}, 50/50 Hockney/Vico, float32, 1% float64 spot checks."""
+def run_serve(args, seconds=None, rate=None, sweep=True):
+    """Poisson arrivals (seed 5), n in {32..256}, 50/50 Hockney/Vico, float32 with 1% float64 spot
+    checks, each request its own 8-Gaussian source (generated on the device before the run),
+    through the serving loop of paper_2405_02603_amd.serve.  Returns the report as a dict."""
     import torch
 
     import workloads as W
     from paper_2405_02603_amd.serve import GpuExecutor, Job, Server
 
+    seconds = args.serve_seconds if seconds is None else seconds
+    rate = args.serve_rate if rate is None else rate
     sizes = (32, 48, 64, 96, 128, 192, 256)
-    reqs = W.poisson_arrivals(rate=args.serve_rate, duration=args.serve_seconds, seed=5, sizes=sizes,
-                              spot_fraction=0.01, blobs=8)
-    pool = {}
-    for n in sizes:
-        r = W.source_density(n, (-1.0,) * 3, (1.0,) * 3, W.multiblob(seed=100 + n))
-        for dt in (torch.float32, torch.float64):
-            pool[(n, dt)] = torch.from_numpy(r).to(dt).pin_memory()
-    ex = GpuExecutor(slots=args.serve_slots, source_for=lambda j, dt: pool[(j.n, dt)])
+    lo, hi = (-1.0,) * 3, (1.0,) * 3
+    arrivals = W.poisson_arrivals(rate=rate, duration=seconds, seed=5, sizes=sizes, spot_fraction=0.01, blobs=8)
+    own = {a.rid: W.source_density_device((a.n,) * 3, lo, hi, a.source, dtype=torch.float32) for a in arrivals}
+    torch.cuda.synchronize()
+    ex = GpuExecutor(slots=args.serve_slots, source_for=lambda j, dt: own[j.rid] if dt == torch.float32
+                     else own[j.rid].to(dt))
     ex.warm([(n, g, p) for n in sizes for g in ("hockney", "vico_dct") for p in ("f32", "f64")])
     budget = int(args.serve_budget_gb * (1 << 30))
 
     def run(scale):
-        jobs = [Job(rid=r.rid, t_arrival=r.t_arrival, n=r.n, greens="hockney" if r.greens == "hockney" else "vico_dct",
-                    spot_check=r.spot_check) for r in reqs]
-        srv = Server(ex, budget_bytes=budget, slots=args.serve_slots)
-        return srv.run(jobs, time_scale=scale)
+        jobs = [Job(rid=a.rid, t_arrival=a.t_arrival, n=a.n, greens="hockney" if a.greens == "hockney" else "vico_dct",
+                    spot_check=a.spot_check) for a in arrivals]
+        return Server(ex, budget_bytes=budget, slots=args.serve_slots).run(jobs, time_scale=scale)
 
     rep = run(1.0)
-    sweep = []
-    for scale in (0.2, 0.05, 0.01, 0.0):
-        r = run(scale)
-        sweep.append({"offered_rate": (args.serve_rate / scale) if scale else "all-at-once",
-                      "solves_per_s": round(r["solves_per_s"], 1), "p50_ms": round(r["p50_ms"], 3),
-                      "p99_ms": round(r["p99_ms"], 3)})
+    out = {"rate": rate, "seconds": seconds, "budget_bytes": budget, **rep}
+    if sweep:
+        sat = []
+        for scale in (0.2, 0.05, 0.0):   # offered 5x, 20x the rate, then everything at once
+            r = run(scale)
+            sat.append({"offered_rate": (rate / scale) if scale else "all-at-once",
+                        "solves_per_s": round(r["solves_per_s"], 1), "p50_ms": round(r["p50_ms"], 3),
+                        "p99_ms": round(r["p99_ms"], 3), "launches": r["launches"]})
+        out["saturation_sweep"] = sat
+    del own, ex
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_serve(args):
+    r = run_serve(args)
     out = {
         "metric": "served solves/s and p50/p99 latency (Poisson arrivals, mixed sizes and kernels)",
-        "value": round(rep["solves_per_s"], 1), "unit": "solves/s", "n_gpus": 1, "steps": rep["done"],
-        "warmup": 0, "ms_per_step": round(1e3 / max(rep["solves_per_s"], 1e-9), 4), "higher_is_better": True,
+        "value": round(r["solves_per_s"], 1), "unit": "solves/s", "n_gpus": 1, "steps": r["done"],
+        "warmup": 0, "ms_per_step": round(1e3 / max(r["solves_per_s"], 1e-9), 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"Poisson arrivals {args.serve_rate}/s for {args.serve_seconds} s, n in {list(sizes)}, "
-                               "50/50 hockney/vico_dct, float32, 1% float64 spot checks, "
-                               f"budget {args.serve_budget_gb} GB, {args.serve_slots} slots"},
-        "p50_ms": round(rep["p50_ms"], 3), "p99_ms": round(rep["p99_ms"], 3), "requests": rep["requests"],
-        "rejected": rep["rejected"], "launches": rep["launches"], "peak_bytes": rep["peak_bytes"],
-        "spot_checks": rep["spot_checks"], "spot_rel_l2_max": rep["spot_rel_l2_max"],
-        "seen_lag_ms": rep["seen_lag_ms"],
-        "saturation_sweep": sweep,
+        "config": {"workload": f"Poisson arrivals {args.serve_rate}/s for {args.serve_seconds} s, n in "
+                               "[32..256], 50/50 hockney/vico_dct, float32, 1% float64 spot checks, each request "
+                               f"its own 8-Gaussian source, budget {args.serve_budget_gb} GB, "
+                               f"{args.serve_slots} slots"},
     }
+    out.update(r)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -563,6 +600,18 @@ def main(argv=None):
             extra["n512"] = bench_large(torch, W, 512, lo, hi, args)
     # a plain device copy of 1 GiB: the bandwidth a streaming kernel reaches on this GPU
     extra["copy_calibration"] = copy_calibration(torch)
+    # compact summaries of the batched (64 uneven right-hand sides per graph launch) and served
+    # (Poisson arrivals at 200/s for 30 s through the native engine) workloads
+    if not args.skip_extras and n == 256:
+        b = run_batch(args, steps=50, warmup=10)
+        extra["batch_64"] = {k: b[k] for k in ("solves_per_s", "ms_per_step", "hbm_frac_model",
+                                                "max_rel_l2_f32_vs_gpu_f64", "sizes")}
+        extra["batch_64"]["fp64_single_solves_per_s"] = b["fp64_single_solves"]["solves_per_s"]
+        sv = run_serve(args, seconds=30.0, rate=200.0)
+        extra["serve_200"] = {k: (round(sv[k], 4) if isinstance(sv[k], float) else sv[k])
+                              for k in ("requests", "done", "rejected", "launches", "p50_ms", "p99_ms",
+                                        "solves_per_s", "budget_bytes", "peak_bytes", "spot_checks",
+                                        "spot_rel_l2_max", "saturation_sweep")}
 
     r32 = results["f32"]
     pb = pass_bytes((n, n, n), r32["rb"])

@@ -36,6 +36,9 @@ EXPORTS = (
     "fsp_solve_grad", "fsp_plan_octant_offset", "fsp_solve_static",
 )
 
+# every symbol include/fsp_serve.h declares
+SERVE_EXPORTS = ("fsp_server_create", "fsp_server_run", "fsp_server_get_stats", "fsp_server_destroy")
+
 # size of the library's static workspace used by fsp_solve_static (FSP_STATIC_SCRATCH_BYTES)
 STATIC_SCRATCH_BYTES = 80 * 1024 * 1024
 
@@ -50,6 +53,49 @@ class PlanDesc(ctypes.Structure):
         ("alpha", c_double),
         ("g0", c_double),
         ("flags", c_uint),
+    ]
+
+
+class Request(ctypes.Structure):
+    """fsp_request (include/fsp_serve.h)."""
+    _fields_ = [
+        ("t_arrival", c_double),
+        ("n", c_int * 3),
+        ("greens", c_int),
+        ("prec", c_int),
+        ("lo", c_double * 3),
+        ("hi", c_double * 3),
+        ("alpha", c_double),
+        ("rho", c_void_p),
+        ("phi", c_void_p),
+    ]
+
+
+class RequestResult(ctypes.Structure):
+    """fsp_request_result (include/fsp_serve.h)."""
+    _fields_ = [
+        ("t_arrival", c_double),
+        ("t_admit", c_double),
+        ("t_done", c_double),
+        ("t_seen", c_double),
+        ("refresh_ms", ctypes.c_float),
+        ("status", c_int),
+        ("slot", c_int),
+        ("launch_size", c_int),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    """fsp_server_stats (include/fsp_serve.h)."""
+    _fields_ = [
+        ("budget_bytes", c_size_t),
+        ("peak_held_bytes", c_size_t),
+        ("held_bytes", c_size_t),
+        ("launches", ctypes.c_longlong),
+        ("refreshes", ctypes.c_longlong),
+        ("evictions", ctypes.c_longlong),
+        ("rejected", ctypes.c_longlong),
+        ("refresh_ms_total", c_double),
     ]
 
 
@@ -100,6 +146,10 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "fsp_plan_model_bytes": (c_int, [P, POINTER(c_double)]),
         "fsp_solve_grad": (c_int, [P, P, P, P, P]),
         "fsp_plan_octant_offset": (c_int, [P, c_int, POINTER(c_size_t)]),
+        "fsp_server_create": (c_int, [c_size_t, c_int, c_int, POINTER(c_void_p)]),
+        "fsp_server_run": (c_int, [P, c_int, POINTER(Request), POINTER(RequestResult), c_double, c_double]),
+        "fsp_server_get_stats": (c_int, [P, POINTER(ServerStats)]),
+        "fsp_server_destroy": (c_int, [P]),
         "fsp_status_str": (c_char_p, [c_int]),
         "fsp_last_error": (c_char_p, []),
         "fsp_version": (c_char_p, []),

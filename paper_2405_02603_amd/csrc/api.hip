@@ -18,6 +18,7 @@
 
 #include "fft_core.hpp"
 #include "fsp.h"
+#include "internal.hpp"
 #include "solve_launch.hpp"
 
 namespace fsp {
@@ -875,6 +876,54 @@ static fsp_status check_batch(const char* who, int count, const fsp_plan* plans,
   }
   return FSP_OK;
 }
+
+}  // extern "C"
+
+// Library-internal entry points of the serving engine (internal.hpp).
+namespace fsp {
+namespace internal {
+
+hipError_t solve_items(fsp_plan geo, int count, const void* const* rho, void* const* phi, void* const* work,
+                       const void* const* octant, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (int i0 = 0; i0 < count && e == hipSuccess; i0 += fsp::MAX_ITEMS) {
+    fsp::SolveGeom g = group_geom(geo);
+    for (int i = i0; i < count && g.items < fsp::MAX_ITEMS; ++i) {
+      const int k = g.items++;
+      g.rho[k] = rho[i];
+      g.phi[k] = phi[i];
+      g.work[k] = work[i];
+      g.ghat[k] = octant[i];
+    }
+    e = run_group(g, geo->d.prec == FSP_F64, 0, 4, s);
+  }
+  return e;
+}
+
+size_t work1_bytes(fsp_plan p) { return p->work1_bytes; }
+size_t ghat_bytes(fsp_plan p) { return p->ghat_bytes; }
+size_t precompute_bytes(fsp_plan p) { return p->pre_bytes; }
+const void* octant(fsp_plan p) { return static_cast<const char*>(p->ghat_read) + p->oct_off; }
+
+fsp_status bind_ghat(fsp_plan p, void* ghat_dev) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip(e, "bind_ghat: hipGetDevice");
+  release_buffers(p);
+  p->device = dev;
+  p->ghat = ghat_dev;
+  p->ghat_read = ghat_dev;
+  p->bound = true;  // no workspace: the plan is only precomputed and read
+  return FSP_OK;
+}
+
+const char* last_error() { return g_err.c_str(); }
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace internal
+}  // namespace fsp
+
+extern "C" {
 
 fsp_status fsp_solve(fsp_plan p, const void* rho, void* phi, void* stream) {
   if (!p || !rho || !phi) return fail(FSP_ERR_INVALID_ARG, "fsp_solve: NULL argument");

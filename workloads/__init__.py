@@ -35,6 +35,7 @@ __all__ = [
     "sphere_density",
     "source_density",
     "random_field",
+    "source_density_device",
     "centred_gaussian",
     "offcentre_gaussian",
     "multiblob",
@@ -116,6 +117,25 @@ def source_density(n, lo, hi, src: Source, dtype=np.float64) -> np.ndarray:
     for (c, r, dens) in src.balls:
         rho = rho + sphere_density(n, lo, hi, c, r, dens)
     return rho.astype(dtype, copy=False)
+
+
+def source_density_device(n, lo, hi, src: Source, dtype=None, device="cuda"):
+    """source_density evaluated with torch on the device (the same cell centres and
+    blob formula, in float64, then cast): a per-request source for serving runs
+    without a host round trip.  Gaussian blobs only."""
+    import torch
+
+    if src.balls:
+        raise ValueError("device sources hold Gaussian blobs only")
+    n = _as3(n, int)
+    x0, x1, x2 = (torch.as_tensor(a, dtype=torch.float64, device=device) for a in axis_centres(n, lo, hi))
+    rho = torch.zeros(n, dtype=torch.float64, device=device)
+    for b in src.blobs:
+        s = float(b.sigma)
+        c = _as3(b.centre)
+        r2 = ((x0 - c[0])[:, None, None] ** 2 + (x1 - c[1])[None, :, None] ** 2 + (x2 - c[2])[None, None, :] ** 2)
+        rho += (b.weight / ((2.0 * np.pi) ** 1.5 * s ** 3)) * torch.exp(-r2 / (2.0 * s * s))
+    return rho if dtype is None else rho.to(dtype)
 
 
 def random_field(n, seed: int, dtype=np.float64) -> np.ndarray:
