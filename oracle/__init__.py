@@ -29,6 +29,9 @@ against the paper by eye:
               invert, restrict); pinned to ``direct``.
 ``exact``     closed-form potentials of the Section 3.1 test sources.
 ``memory``    the field-memory formulas of Section 3.3.
+``mixed``     mixed open / periodic axes (Section 2.2, step 1: only the open
+              axes are doubled): the plain sum with nearest-image offsets on
+              the periodic axes, and the FFT route with only open axes doubled.
 
 Parity pins (tests/test_oracle_*.py): ``fftroute`` equals ``direct`` to
 rounding; ``direct`` equals a pure-Python six-loop sum on tiny grids; the three
@@ -39,9 +42,9 @@ of Section 3.1; linearity, translation and symmetry hold; the memory formulas
 reproduce Table 2.  No function in this package is "parity unpinned".
 """
 
-from . import greens, direct, fftroute, exact, memory  # noqa: F401
+from . import greens, direct, fftroute, exact, memory, mixed  # noqa: F401
 
-__all__ = ["greens", "direct", "fftroute", "exact", "memory", "rel_l2"]
+__all__ = ["greens", "direct", "fftroute", "exact", "memory", "mixed", "rel_l2"]
 
 
 def rel_l2(a, b) -> float:
