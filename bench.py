@@ -110,10 +110,10 @@ def parse(argv=None):
     ap.add_argument("--skip-f64", action="store_true")
     ap.add_argument("--skip-extras", action="store_true", help="skip the gradient and precompute timings")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule")
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve", "shard"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "serve", "shard", "grad"],
                     help="single: the 256^3 headline; batch: 64 uneven right-hand sides per graph launch; "
                          "serve: Poisson-arrival serving loop; shard: one GPU's share of an 8-way "
-                         "slab-decomposed solve, at its real shapes")
+                         "slab-decomposed solve, at its real shapes; grad: phi and its gradient in one call")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -296,6 +296,25 @@ def bench_grad(torch, W, n, lo, hi, src, args):
         del plan, rho, phi, grad
         torch.cuda.empty_cache()
     return out
+
+
+def bench_grad_line(args):
+    """phi and grad phi of the 256^3 8-Gaussian workload in one call, both precisions, as its own line."""
+    import torch
+
+    import workloads as W
+
+    n = args.n
+    lo, hi = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+    r = bench_grad(torch, W, n, lo, hi, W.multiblob(seed=3, count=8), args)
+    out = {"metric": f"phi and grad phi solves/s, {n}^3 {args.greens}", "value": round(1e3 / r["f32"]["ms"], 2),
+           "unit": "solves/s", "n_gpus": 1, "steps": max(10, args.steps // 4), "warmup": 5,
+           "ms_per_step": r["f32"]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{args.greens} potential and gradient, {n}^3 on [-1,1]^3, 8 Gaussians (seed 3)"},
+           "grad": r}
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def bench_large(torch, W, n, lo, hi, args):
@@ -546,6 +565,8 @@ def main(argv=None):
         return bench_serve(args)
     if args.workload == "shard":
         return bench_shard(args)
+    if args.workload == "grad":
+        return bench_grad_line(args)
 
     import numpy as np
     import torch
@@ -608,7 +629,7 @@ def main(argv=None):
                                                 "max_rel_l2_f32_vs_gpu_f64", "sizes")}
         extra["batch_64"]["fp64_single_solves_per_s"] = b["fp64_single_solves"]["solves_per_s"]
         sv = run_serve(args, seconds=30.0, rate=200.0)
-        extra["serve_200"] = {k: (round(sv[k], 4) if isinstance(sv[k], float) else sv[k])
+        extra["serve_200"] = {k: (float(f"{sv[k]:.5g}") if isinstance(sv[k], float) else sv[k])
                               for k in ("requests", "done", "rejected", "launches", "p50_ms", "p99_ms",
                                         "solves_per_s", "budget_bytes", "peak_bytes", "spot_checks",
                                         "spot_rel_l2_max", "saturation_sweep")}

@@ -72,6 +72,18 @@ typedef enum { FSP_F32 = 0, FSP_F64 = 1 } fsp_prec;
  * octants in the Green's buffer) and size the workspace for fsp_solve_grad
  * (four spectra instead of one). */
 #define FSP_WANT_GRAD 1u
+/* Periodic axes (Section 2.2, step 1: the grid is doubled only along the axes
+ * with open boundaries).  Along a periodic axis a of n_a points the solve is a
+ * cyclic convolution of period n_a whose Green's function takes, at offset d,
+ * its value at the nearest image (min(d, n_a - d)): the Green's function
+ * circularly shifted over the axis's own period, as step 3 shifts it over the
+ * doubled period of an open axis.  The transform tables fold each periodic
+ * axis that way; the passes are those of the open solve (the doubled cyclic
+ * convolution with the folded table equals the n_a-periodic one).  Any Green's
+ * function; not with FSP_WANT_GRAD (FSP_ERR_INVALID_ARG). */
+#define FSP_PERIODIC_0 2u
+#define FSP_PERIODIC_1 4u
+#define FSP_PERIODIC_2 8u
 
 typedef struct {
   int n[3];          /* grid points per axis; axis 2 is contiguous                     */
@@ -81,7 +93,7 @@ typedef struct {
   int prec;          /* fsp_prec: precision of rho, phi and the solve passes            */
   double alpha;      /* Vico-Greengard window factor, L = alpha |hi - lo|; 0 -> 1.1     */
   double g0;         /* Hockney-Eastwood K[0]; NaN -> 1/(4 pi)                           */
-  unsigned flags;    /* FSP_FLAG_NONE or FSP_WANT_GRAD; other bits: FSP_ERR_INVALID_ARG */
+  unsigned flags;    /* FSP_WANT_GRAD, FSP_PERIODIC_*; other bits: FSP_ERR_INVALID_ARG  */
 } fsp_plan_desc;
 
 /* Validate a descriptor and build a plan.  Host only: no device memory is

@@ -68,11 +68,13 @@ class Plan:
     ``prec``: "f32" or "f64" (precision of rho, phi and the solve passes; the
     precompute always runs in float64).
     ``grad``: also build the derivative tables for ``solve_grad``.
+    ``periodic``: per axis, a periodic boundary instead of an open one (see FSP_PERIODIC_0 in fsp.h).
     """
 
     def __init__(self, n, lo=(-0.5, -0.5, -0.5), hi=(0.5, 0.5, 0.5), greens: str = "vico_dct",
                  prec: str = "f32", alpha: float = 1.1, g0: Optional[float] = None, device=None,
-                 precompute: bool = True, stream=None, bind: bool = True, grad: bool = False):
+                 precompute: bool = True, stream=None, bind: bool = True, grad: bool = False,
+                 periodic=(False, False, False)):
         torch = _torch()
         self._lib = _lib.load()
         if greens not in GREENS:
@@ -99,7 +101,9 @@ class Plan:
         desc.alpha = self.alpha
         desc.g0 = float("nan") if g0 is None else float(g0)
         self.grad = bool(grad)
-        desc.flags = _lib.FSP_WANT_GRAD if self.grad else 0
+        self.periodic = tuple(bool(x) for x in periodic)
+        desc.flags = (_lib.FSP_WANT_GRAD if self.grad else 0) | sum(
+            f for f, on in zip(_lib.FSP_PERIODIC, self.periodic) if on)
         h = ctypes.c_void_p()
         check(self._lib.fsp_plan_create(ctypes.byref(desc), ctypes.byref(h)), "fsp_plan_create")
         self._h = h

@@ -32,6 +32,7 @@ hipError_t greens_contract_axis(const double* X, double* Y, const double* packed
                                 const long long dims[3], int axis, int nout, hipStream_t s);
 void greens_pack_contract(std::vector<double>& out, const std::vector<double>& ce, const std::vector<double>* co,
                           int nout, int kin, int period);
+hipError_t greens_fold_periodic(const double* X, double* Y, const int n[3], int periodic, hipStream_t s);
 hipError_t greens_store_octant(const double* G, void* out, bool f64, const int n[3], int tile, double scale,
                                hipStream_t s);
 int conv_tile_f32(int L);
@@ -268,6 +269,7 @@ struct fsp_plan_s {
   int gather_min = fsp::CONV_GATHER_MIN_BLOCKS;  // axis-0 grid size from which the lone column is gathered
   size_t tw_row_off[fsp::NUM_PLANS]{}, tw_c1_off[fsp::NUM_PLANS]{}, tw_c0_off[fsp::NUM_PLANS]{}, oct_off = 0;
   bool grad = false;        // FSP_WANT_GRAD: derivative octants and three more spectra
+  int periodic = 0;         // bit a: axis a periodic (its kernel table folded to the nearest image)
   size_t grad_off[3]{};     // offsets of the derivative octants in the Green's buffer
   int grad_p3 = -1;         // axis-0 variant of the gradient solve (-1: from the schedule)
   size_t work1_bytes = 0;   // one workspace S (the gradient's other spectra follow it)
@@ -383,7 +385,11 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     if (d.greens == FSP_VICO && d.n[a] > 256)
       return fail(FSP_ERR_UNSUPPORTED_SIZE, "fsp_plan_create: the (4N)^3 Vico-Greengard route is limited to n <= 256");
   }
-  if (d.flags & ~(unsigned)FSP_WANT_GRAD) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: unknown flags");
+  const unsigned periodic_bits = FSP_PERIODIC_0 | FSP_PERIODIC_1 | FSP_PERIODIC_2;
+  if (d.flags & ~((unsigned)FSP_WANT_GRAD | periodic_bits))
+    return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: unknown flags");
+  if ((d.flags & FSP_WANT_GRAD) && (d.flags & periodic_bits))
+    return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: periodic axes are not supported with FSP_WANT_GRAD");
   const double alpha = d.alpha == 0.0 ? 1.1 : d.alpha;
   if (!std::isfinite(alpha) || !(alpha > 1.0))
     return fail(FSP_ERR_INVALID_ARG, "fsp_plan_create: alpha must exceed 1 (0 selects 1.1)");
@@ -391,6 +397,8 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
   if (!p) return fail(FSP_ERR_OUT_OF_MEMORY, "fsp_plan_create: host allocation failed");
   p->d = d;
   p->alpha = alpha;
+  p->periodic = ((d.flags & FSP_PERIODIC_0) ? 1 : 0) | ((d.flags & FSP_PERIODIC_1) ? 2 : 0) |
+                ((d.flags & FSP_PERIODIC_2) ? 4 : 0);
   p->g0 = std::isnan(d.g0) ? 1.0 / (4.0 * M_PI) : d.g0;
   double diag2 = 0, minlen = 1e300;
   for (int a = 0; a < 3; ++a) {
@@ -562,7 +570,8 @@ fsp_status fsp_plan_bind(fsp_plan p, void* ghat_dev, void* work_dev) {
 fsp_status fsp_plan_share_ghat(fsp_plan dst, fsp_plan src) {
   if (!dst || !src) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_share_ghat: NULL plan");
   const fsp_plan_desc &a = dst->d, &b = src->d;
-  bool same = a.greens == b.greens && a.prec == b.prec && dst->alpha == src->alpha && dst->g0 == src->g0;
+  bool same = a.greens == b.greens && a.prec == b.prec && dst->alpha == src->alpha && dst->g0 == src->g0 &&
+              dst->periodic == src->periodic;
   for (int i = 0; i < 3; ++i) same = same && a.n[i] == b.n[i] && a.lo[i] == b.lo[i] && a.hi[i] == b.hi[i];
   if (!same) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_share_ghat: plans differ in kernel, grid, box or precision");
   if (dst->grad && !src->grad)
@@ -750,6 +759,10 @@ fsp_status fsp_precompute(fsp_plan p, void* stream) {
       for (int a = 0; a < 3; ++a) contract(n[a] + 1);
       // inverse transform on the 4n grid: 1 / prod(4 n_d h_d) = 1 / (64 n0 n1 n2 V)
       scale /= 64.0 * n0 * n1 * n2 * p->V;
+    }
+    if (p->periodic && e == hipSuccess) {  // the kernel octant (in X) folded to the nearest image
+      e = fsp::greens_fold_periodic(X, Y, n, p->periodic, s);
+      std::swap(X, Y);
     }
     for (int a = 0; a < 3; ++a) contract(n[a] + 1);
     const size_t off = comp == 0 ? p->oct_off : p->grad_off[comp - 1];

@@ -94,6 +94,24 @@ __global__ __launch_bounds__(256) void k_vico_spectrum(double* G, int s0, int s1
   G[i] = v;
 }
 
+// Periodic axes: Y[m] = X[f0(m0)][f1(m1)][f2(m2)] on the (n+1)^3 octant, with
+// f_a(m) = min(m, n_a - m) on a periodic axis (bit a of `periodic`), m on an
+// open one: the kernel at each offset's nearest image over the axis's period.
+__global__ __launch_bounds__(256) void k_fold_periodic(const double* __restrict__ X, double* __restrict__ Y, int n0,
+                                                       int n1, int n2, int periodic) {
+  const long long total = (long long)(n0 + 1) * (n1 + 1) * (n2 + 1);
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  int m2 = (int)(i % (n2 + 1));
+  const long long t = i / (n2 + 1);
+  int m1 = (int)(t % (n1 + 1));
+  int m0 = (int)(t / (n1 + 1));
+  if (periodic & 1) m0 = m0 < n0 - m0 ? m0 : n0 - m0;
+  if (periodic & 2) m1 = m1 < n1 - m1 ? m1 : n1 - m1;
+  if (periodic & 4) m2 = m2 < n2 - m2 ? m2 : n2 - m2;
+  Y[i] = X[((long long)m0 * (n1 + 1) + m1) * (n2 + 1) + m2];
+}
+
 // Store the octant G[k0][k1][k2] (float64, dense) scaled, in the blocked layout
 // out[((k1 * tiles + k2 / tile) * (n0 + 1) + k0) * tile + k2 % tile]; slots of
 // the last tile beyond k2 = n2 are zero.
@@ -127,6 +145,12 @@ hipError_t greens_he_grad_kernel(double* D, const int n[3], const double h[3], i
   const long long total = (long long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
   hipLaunchKernelGGL(k_he_grad_kernel, dim3(grid1(total)), dim3(256), 0, s, D, n[0], n[1], n[2], h[0], h[1], h[2],
                      axis);
+  return hipGetLastError();
+}
+
+hipError_t greens_fold_periodic(const double* X, double* Y, const int n[3], int periodic, hipStream_t s) {
+  const long long total = (long long)(n[0] + 1) * (n[1] + 1) * (n[2] + 1);
+  hipLaunchKernelGGL(k_fold_periodic, dim3(grid1(total)), dim3(256), 0, s, X, Y, n[0], n[1], n[2], periodic);
   return hipGetLastError();
 }
 

@@ -225,7 +225,8 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   constexpr bool GRAD = NOUT > 0;
   constexpr int K = plan_len(L, PID);
   static_assert(!TWF || K > 1, "single-stage plans have no twiddles");
-  constexpr bool PRE = K == 2 && !TWF && !GRAD && sizeof(T) == 4;  // the others keep their registers for occupancy
+  // the others keep their registers for occupancy (at 1024 points the preloaded values spill)
+  constexpr bool PRE = K == 2 && !TWF && !GRAD && sizeof(T) == 4 && L <= 512;
   constexpr int NT = TC * NQ;
   constexpr int TWN = TWF ? (twf_size(L, PID) + NT - 1) / NT : 1;  // table entries per thread
   __shared__ cx<T> lds[K > 1 ? L * TC : 1];

@@ -167,9 +167,9 @@ def test_schedule_validation(lib):
 
 
 def test_gradient_plan_sizes_offsets_and_errors(lib):
-    # unknown flag bits are rejected
+    # unknown flag bits are rejected (bits 1-3 are the periodic axes)
     d = _desc(n=32)
-    d.flags = 2
+    d.flags = 16
     assert _create(lib, d)[0] == _lib.FSP_ERR_INVALID_ARG
     # a plan without FSP_WANT_GRAD: one octant, one workspace, no derivative tables
     st, h0 = _create(lib, _desc(n=(16, 24, 32)))
@@ -268,3 +268,21 @@ def test_autotune_rejects_aliased_rho_phi(lib):
     r = lib.fsp_autotune(h, ctypes.c_void_p(base), ctypes.c_void_p(base + field), 2, None, None)
     assert r == _lib.FSP_ERR_NOT_READY
     lib.fsp_plan_destroy(h)
+
+
+def test_periodic_flags(lib):
+    """Periodic-axis flags are accepted on every axis and Green's function; they cannot be
+    combined with FSP_WANT_GRAD."""
+    for greens in (0, 1, 2):
+        for bit in (2, 4, 8, 14):
+            d = _desc(n=16, greens=greens)
+            d.flags = bit
+            st, h = _create(lib, d)
+            assert st == _lib.FSP_OK, (greens, bit)
+            lib.fsp_plan_destroy(h)
+    d = _desc(n=16)
+    d.flags = 1 | 4
+    assert _create(lib, d)[0] == _lib.FSP_ERR_INVALID_ARG
+    assert b"FSP_WANT_GRAD" in lib.fsp_last_error()
+    d.flags = 16
+    assert _create(lib, d)[0] == _lib.FSP_ERR_INVALID_ARG
