@@ -123,3 +123,55 @@ def test_serve_rejects_over_budget(torch_cuda):
     assert jobs[0].status == "rejected"
     assert jobs[1].status == "done"
     assert rep["done"] == 1 and rep["rejected"] == 1
+
+
+BOXES = [((-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)),
+         ((-0.8, -1.2, -1.0), (1.1, 0.9, 1.3)),
+         ((-0.6, -0.7, -0.9), (0.7, 0.8, 0.6)),
+         ((-1.5, -1.0, -1.0), (1.5, 1.2, 0.9))]
+
+
+def test_serve_varying_boxes_under_a_tight_budget(torch_cuda):
+    """Requests whose box changes from one to the next (a domain fitted to the particles):
+    every box's Green's transform is computed on a miss, on the precompute stream, and
+    timed; the budget covers the transforms and workspaces kept between requests, so it
+    forces evictions; device memory never exceeds it; and every result is the oracle's
+    at its own box and kernel."""
+    torch = torch_cuda
+    from paper_2405_02603_amd.serve import GpuExecutor, Job, Server, field_bytes
+
+    rng = np.random.default_rng(17)
+    jobs, t = [], 0.0
+    for rid in range(40):
+        t += float(rng.exponential(1.0 / 300.0))
+        lo, hi = BOXES[int(rng.integers(0, len(BOXES)))]
+        jobs.append(Job(rid=rid, t_arrival=t, n=int((32, 48)[rid % 2]), greens=("vico_dct", "hockney")[(rid // 2) % 2],
+                        lo=lo, hi=hi))
+    host = {j.rid: W.source_density(j.n, j.lo, j.hi, W.multiblob(seed=2000 + j.rid)) for j in jobs}
+    pinned = {rid: torch.from_numpy(h).to(torch.float32).pin_memory() for rid, h in host.items()}
+    ex = GpuExecutor(slots=3, source_for=lambda j, dt: pinned[j.rid], keep_results=True)
+    keys = {ex.key_for(j.n, j.greens, j.prec, j.lo, j.hi) for j in jobs}
+    alone = max(ex.resident.alone(k) for k in keys) + field_bytes(48, "f32")
+    held_all = sum(sum(ex._sizes(k)[:2]) for k in keys)
+    budget = 2 * alone
+    assert budget < held_all, "the budget must not hold every transform at once"
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    srv = Server(ex, budget_bytes=budget, slots=3)
+    rep = srv.run(jobs)
+    torch.cuda.synchronize()
+    kept = sum(field_bytes(j.n, "f32") // 2 for j in jobs)
+    print("varying boxes", {k: rep[k] for k in ("done", "launches", "peak_bytes", "budget_bytes", "resident", "refresh")})
+    assert rep["done"] == len(jobs), rep
+    assert rep["peak_bytes"] <= budget
+    assert torch.cuda.max_memory_allocated() - base <= budget + kept + (1 << 20)
+    res, rf = rep["resident"], rep["refresh"]
+    assert res["evictions"] > 0 and res["misses"] >= len(keys) and res["hits"] > 0
+    assert rf["refreshes"] == res["misses"] and rf["refresh_ms_total"] > 0 and 0 < rf["refresh_share"] < 1
+    assert rf["requests_refreshed"] >= 1
+    for j in jobs:
+        ref = reference(host[j.rid], j.greens, j.lo, j.hi, use_direct=False)
+        got = to_host(ex.results[j.rid])
+        assert rel_l2(got, ref) <= 1e-6, (j.rid, j.n, j.greens, j.lo, j.hi)
+        assert elem_err(got, ref) <= F32_ELEM, (j.rid, j.n, j.greens, j.lo, j.hi)

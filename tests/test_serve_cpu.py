@@ -146,3 +146,114 @@ def test_server_loop_on_host_clock():
         assert j.t_seen >= j.t_done
     assert rep["seen_lag_ms"]["min"] >= 0.0
     assert rep["p99_ms"] >= rep["p50_ms"] >= 2.0
+
+
+# ------------------------------------------------------------------ resident set
+from paper_2405_02603_amd.serve import ResidentSet  # noqa: E402
+
+SIZES = {"a": (100, 50, 400), "b": (200, 50, 400), "c": (300, 50, 400), "d": (100, 50, 900)}
+
+
+def _res(log=None):
+    return ResidentSet(lambda k: SIZES[k[0]], (lambda e, i: log.append((e.key, i))) if log is not None else None)
+
+
+def test_resident_reserve_release_and_extra_slots():
+    r = _res()
+    assert r.peek(("a",)) == 550 and r.bytes() == 0
+    t1 = r.reserve(("a",))
+    assert t1.created and t1.index == 0
+    assert r.bytes() == 100 + 50 + 400           # transform, home workspace, refresh transient
+    assert r.peek(("a",)) == 50                  # the home plan is busy: one more workspace
+    t2 = r.reserve(("a",))
+    assert not t2.created and t2.index == 1 and r.bytes() == 100 + 2 * 50 + 400
+    r.release(t1)
+    assert r.bytes() == 100 + 2 * 50              # the transient ends with the job that carried it
+    assert r.peek(("a",)) == 0
+    r.release(t2)
+    assert r.entries[("a",)].refs == 0 and r.hits == 1 and r.misses == 1
+
+
+def test_resident_evicts_idle_workspaces_then_lru_entries():
+    log = []
+    r = _res(log)
+    ta, tb, tc = (r.reserve((k,)) for k in "abc")
+    ta2 = r.reserve(("a",))                       # an extra workspace for "a"
+    for t in (ta, tb, tc, ta2):
+        r.release(t)
+    r.release(r.reserve(("a",)))                 # touch "a": now most recently used
+    assert list(r.entries) == [("b",), ("c",), ("a",)]
+    freed = r.evict(10)                          # the idle extra workspace is enough
+    assert freed == 50 and log == [(("a",), 1)]
+    freed = r.evict(201)                         # then "b" (250) as least recently used
+    assert freed == 250 and log[-1] == (("b",), None) and ("b",) not in r.entries
+    assert r.evictions == 1
+
+
+def test_resident_never_evicts_what_a_ticket_uses():
+    r = _res()
+    t = r.reserve(("c",))
+    assert r.evict(10_000) == 0 and ("c",) in r.entries
+    r.release(t)
+    assert r.evict(10_000) == 350 and not r.entries
+
+
+def test_scheduler_counts_resident_bytes_in_the_budget():
+    r = _res()
+    s = Scheduler(budget_bytes=1200, slots=4, resident=r)
+    jobs = [Job(rid=i, t_arrival=0.0, n=8, greens="x", nbytes=100, rkeys=((k,),)) for i, k in enumerate("abc")]
+    for j in jobs:
+        assert s.submit(j)
+    got = s.admit(0.0)
+    # a: 100 + 550 = 650; b would add 100 + 650 -> 1400 > 1200: it waits, c behind it
+    assert [[j.rid for j in g] for _, g in got] == [[0]] and s.held() == 650
+    s.complete(got[0][0], 1.0)
+    assert s.held() == 150                       # a's transform and home workspace stay resident
+    got = s.admit(1.0)
+    assert [[j.rid for j in g] for _, g in got] == [[1]] and s.held() == 150 + 100 + 650
+    s.complete(got[0][0], 2.0)
+    got = s.admit(2.0)                           # c needs 850 beside 400 resident: a is evicted
+    assert [[j.rid for j in g] for _, g in got] == [[2]]
+    assert ("a",) not in r.entries and r.evictions == 1 and s.held() <= 1200
+
+
+def test_scheduler_rejects_what_cannot_fit_alone():
+    s = Scheduler(budget_bytes=1000, slots=1, resident=_res())
+    j = Job(rid=0, t_arrival=0.0, n=8, greens="x", nbytes=100, rkeys=(("d",),))   # 100 + 1050
+    assert not s.submit(j) and j.status == "rejected"
+
+
+def test_simulated_run_with_resident_set_respects_budget():
+    rnd = random.Random(11)
+    sizes = {}
+
+    def size(key):
+        if key not in sizes:
+            sizes[key] = (rnd.randint(50, 400), rnd.randint(20, 200), rnd.randint(100, 800))
+        return sizes[key]
+
+    r = ResidentSet(size)
+    budget = 4000
+    s = Scheduler(budget_bytes=budget, slots=3, max_fold=4, resident=r)
+    jobs = []
+    for i in range(300):
+        n = rnd.choice([8, 16])
+        box = rnd.randrange(6)                   # boxes change: six extents per grid
+        keys = ((n, box, "f32"),) + (((n, box, "f64"),) if i % 17 == 0 else ())
+        jobs.append(Job(rid=i, t_arrival=i * 0.01, n=n, greens="x", nbytes=rnd.randint(50, 500), rkeys=keys,
+                        spot_check=len(keys) > 1))
+    for j in jobs:
+        s.submit(j)
+    t, running = 0.0, []
+    while s.queue or s.busy:
+        for slot, g in s.admit(t):
+            running.append((t + 0.05 * len(g), slot))
+        assert s.held() <= budget
+        running.sort()
+        t, slot = running.pop(0)
+        s.complete(slot, t)
+        assert s.held() <= budget
+    assert all(j.status == "done" for j in jobs)
+    assert s.peak_bytes <= budget and s.in_use == 0 and r.transient == 0
+    assert r.evictions > 0 and r.hits > 0
+    assert all(e.refs == 0 for e in r.entries.values())

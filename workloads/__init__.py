@@ -218,3 +218,18 @@ def poisson_arrivals(rate: float = 200.0, duration: float = 30.0, seed: int = 5,
         out.append(Request(rid, t, n, greens, spot, src))
         rid += 1
     return out
+
+
+def fitted_box(src: Source, margin_sigmas: float = 4.0, quantum: float = 0.25, min_edge: float = 1.25):
+    """A domain fitted to a source: the bounding box of its blobs' centres widened by
+    ``margin_sigmas`` sigma, each edge widened about its middle to at least
+    ``min_edge``, each face then moved outward to a multiple of ``quantum`` (so that
+    nearby fits share a box).  Returns (lo, hi)."""
+    c = np.array([b.centre for b in src.blobs], dtype=np.float64)
+    s = np.array([b.sigma for b in src.blobs], dtype=np.float64)[:, None]
+    lo = (c - margin_sigmas * s).min(axis=0)
+    hi = (c + margin_sigmas * s).max(axis=0)
+    short = np.maximum(min_edge - (hi - lo), 0.0) / 2
+    lo = np.floor((lo - short) / quantum) * quantum
+    hi = np.ceil((hi + short) / quantum) * quantum
+    return tuple(float(x) for x in lo), tuple(float(x) for x in hi)
