@@ -420,7 +420,12 @@ class GpuExecutor:
                 home = self.Plan(n=n, lo=lo, hi=hi, greens=greens, prec=prec, alpha=alpha,
                                  device=self.device, precompute=False)
                 start.record(self.pre_stream)
-                home.precompute(self.pre_stream)
+                try:
+                    home.precompute(self.pre_stream)
+                except Exception:
+                    # part of it may be enqueued: let it end before the buffers go
+                    self.pre_stream.synchronize()
+                    raise
                 end.record(self.pre_stream)
             e.plans[0] = home
             e.handle = end
@@ -482,55 +487,66 @@ class GpuExecutor:
 
     # -------------------------------------------------------------- launches
     def launch(self, slot: int, group: List[Job]) -> None:
-        from . import solve_batched
+        """Enqueue one slot launch.  A launch that cannot get its device memory (a
+        plan's buffers, a result) fails alone: whatever it enqueued before the
+        failure still completes before its tensors are released, and the loop goes
+        on serving."""
+        from . import FspError, solve_batched
 
         torch = self.torch
         st = self.streams[slot]
         prec = group[0].prec
         dt = torch.float64 if prec == "f64" else torch.float32
         plans, rhos, outs = [], [], []
+        held = [rhos, outs]
+        err = None
         with torch.cuda.stream(st):
-            for j in group:
-                t = j.tickets[0]
-                plans.append(self._plan(t))
-                j.refreshed = self._await(t, st)
-                src = self.source_for(j, dt)
-                rho = src if src.device == self.device else src.to(self.device, non_blocking=True)
-                rhos.append(rho)
-                outs.append(torch.empty_like(rho))
-            solve_batched(plans, rhos, outs, stream=st)
-            held = [rhos, outs]
-            if group[0].spot_check:
-                j = group[0]
-                t64 = j.tickets[1]
-                p64 = self._plan(t64)
-                j.refreshed = self._await(t64, st) or j.refreshed
-                r64 = rhos[0].double()
-                o64 = p64.solve(r64, stream=st)
-                diff = torch.linalg.vector_norm((outs[0].double() - o64).flatten())
-                den = torch.linalg.vector_norm(o64.flatten())
-                held += [r64, o64, diff, den]
+            try:
+                for j in group:
+                    t = j.tickets[0]
+                    plans.append(self._plan(t))
+                    j.refreshed = self._await(t, st)
+                    src = self.source_for(j, dt)
+                    rho = src if src.device == self.device else src.to(self.device, non_blocking=True)
+                    rhos.append(rho)
+                    outs.append(torch.empty_like(rho))
+                solve_batched(plans, rhos, outs, stream=st)
+                if group[0].spot_check:
+                    j = group[0]
+                    t64 = j.tickets[1]
+                    p64 = self._plan(t64)
+                    j.refreshed = self._await(t64, st) or j.refreshed
+                    r64 = rhos[0].double()
+                    held.append(r64)
+                    o64 = p64.solve(r64, stream=st)
+                    held.append(o64)
+                    diff = torch.linalg.vector_norm((outs[0].double() - o64).flatten())
+                    den = torch.linalg.vector_norm(o64.flatten())
+                    held += [diff, den]
+            except (FspError, torch.cuda.OutOfMemoryError) as e:
+                err = f"{type(e).__name__}: {e}"
             done = torch.cuda.Event(enable_timing=True)
             done.record(st)
-        self.inflight[slot] = (done, group, held)
+        self.inflight[slot] = (done, group, held, err)
 
-    def poll(self) -> List[Tuple[int, float]]:
-        """(slot, completion time in seconds since start) of launches that finished."""
+    def poll(self) -> List[Tuple[int, float, Optional[str]]]:
+        """(slot, completion time in seconds since start, error or None) of launches that finished."""
         out = []
-        for slot, (ev, group, held) in list(self.inflight.items()):
+        for slot, (ev, group, held, err) in list(self.inflight.items()):
             if ev.query():
                 t = self.t0_event.elapsed_time(ev) / 1e3  # GPU clock, seconds since start
-                if group[0].spot_check and len(held) > 2:
+                if err is None and group[0].spot_check:
                     diff, den = held[-2], held[-1]
                     group[0].spot_rel_l2 = float(diff / den)
                 for j in group:
                     for tk in j.tickets:   # the launch waited for these transforms
-                        tk.entry.pending_pre = False
-                if self.keep_results:
+                        if tk.entry.handle is not None and tk.entry.handle.query():
+                            tk.entry.pending_pre = False
+                if self.keep_results and err is None:
                     for j, o in zip(group, held[1]):
                         self.results[j.rid] = o
                 del self.inflight[slot]
-                out.append((slot, t))
+                out.append((slot, t, err))
         return out
 
     def refresh_stats(self) -> Dict:
@@ -571,9 +587,10 @@ class Server:
                 j = pending.popleft()
                 j.t_arrival *= time_scale
                 self.sched.submit(j)
-            for slot, t in self.ex.poll():
+            for done in self.ex.poll():
+                slot, t = done[0], done[1]
                 seen = self.ex.now()
-                for j in self.sched.complete(slot, t):
+                for j in self.sched.complete(slot, t, failed=done[2] if len(done) > 2 else None):
                     j.t_seen = seen
             for slot, group in self.sched.admit(now):
                 self.ex.launch(slot, group)
@@ -599,6 +616,7 @@ class Server:
             "requests": len(self.jobs),
             "done": len(done),
             "rejected": sum(j.status == "rejected" for j in self.jobs),
+            "failed": sum(j.status == "failed" for j in self.jobs),
             "launches": launches,
             "p50_ms": percentile(lat, 50),
             "p99_ms": percentile(lat, 99),

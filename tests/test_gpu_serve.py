@@ -175,3 +175,47 @@ def test_serve_varying_boxes_under_a_tight_budget(torch_cuda):
         got = to_host(ex.results[j.rid])
         assert rel_l2(got, ref) <= 1e-6, (j.rid, j.n, j.greens, j.lo, j.hi)
         assert elem_err(got, ref) <= F32_ELEM, (j.rid, j.n, j.greens, j.lo, j.hi)
+
+
+def test_serve_survives_a_failed_allocation(torch_cuda):
+    """A plan that cannot get its device memory (forced on the host: the executor's third
+    buffer-owning plan, the first 64^3 request's, raises FSP_ERR_OUT_OF_MEMORY) fails its
+    launch alone; the next 64^3 request builds that plan again, every other
+    request is served and matches the oracle, and the executor serves a later run whole."""
+    torch = torch_cuda
+    from paper_2405_02603_amd import FspError, _lib
+    from paper_2405_02603_amd.serve import GpuExecutor, Job, Server
+
+    def jobs_from(base, count):
+        return [Job(rid=base + i, t_arrival=0.0005 * i, n=(32, 48, 64)[i % 3], greens="hockney") for i in range(count)]
+
+    first, second = jobs_from(0, 10), jobs_from(100, 10)
+    host = {j.rid: W.source_density(j.n, (-1.0,) * 3, (1.0,) * 3, W.multiblob(seed=3000 + j.rid))
+            for j in first + second}
+    pinned = {rid: torch.from_numpy(h).to(torch.float32).pin_memory() for rid, h in host.items()}
+    ex = GpuExecutor(slots=2, source_for=lambda j, dt: pinned[j.rid], keep_results=True)
+    real_plan, made = ex.Plan, [0]
+
+    def plan_factory(*args, **kw):
+        if kw.get("bind", True):
+            made[0] += 1
+            if made[0] == 3:
+                raise FspError(_lib.FSP_ERR_OUT_OF_MEMORY, "fsp_plan_bind: FSP_ERR_OUT_OF_MEMORY: injected")
+        return real_plan(*args, **kw)
+
+    ex.Plan = plan_factory
+    rep = Server(ex, budget_bytes=1 << 30, slots=2, max_fold=1).run(first)
+    torch.cuda.synchronize()
+    failed = [j for j in first if j.status == "failed"]
+    assert rep["failed"] == len(failed) == 1 and "OUT_OF_MEMORY" in failed[0].error, rep
+    assert failed[0].rid == 2 and failed[0].n == 64
+    assert rep["done"] == len(first) - 1
+    rep2 = Server(ex, budget_bytes=1 << 30, slots=2, max_fold=1).run(second)
+    torch.cuda.synchronize()
+    assert rep2["done"] == len(second) and rep2["failed"] == 0
+    for j in first + second:
+        if j.status != "done":
+            continue
+        ref = reference(host[j.rid], "hockney", (-1.0,) * 3, (1.0,) * 3, use_direct=False)
+        got = to_host(ex.results[j.rid])
+        assert rel_l2(got, ref) <= 1e-6 and elem_err(got, ref) <= F32_ELEM, (j.rid, j.n)

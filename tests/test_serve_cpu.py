@@ -257,3 +257,30 @@ def test_simulated_run_with_resident_set_respects_budget():
     assert s.peak_bytes <= budget and s.in_use == 0 and r.transient == 0
     assert r.evictions > 0 and r.hits > 0
     assert all(e.refs == 0 for e in r.entries.values())
+
+
+class _FailingExecutor(_HostExecutor):
+    """Host stand-in whose second launch fails (as a launch whose plan cannot get its memory)."""
+
+    def __init__(self):
+        super().__init__(service=0.001)
+        self.launches = 0
+        self.errors = {}
+
+    def launch(self, slot, group):
+        self.launches += 1
+        super().launch(slot, group)
+        self.errors[slot] = "FspError: FSP_ERR_OUT_OF_MEMORY" if self.launches == 2 else None
+
+    def poll(self):
+        return [(s, t, self.errors.pop(s)) for s, t in super().poll()]
+
+
+def test_server_keeps_serving_after_a_failed_launch():
+    ex = _FailingExecutor()
+    srv = Server(ex, budget_bytes=8 << 20, slots=1, max_fold=1)
+    jobs = [_job(i, n=32, t=0.002 * i) for i in range(10)]
+    rep = srv.run(jobs)
+    assert rep["failed"] == 1 and rep["done"] == 9
+    assert jobs[1].status == "failed" and "OUT_OF_MEMORY" in jobs[1].error
+    assert srv.sched.in_use == 0
