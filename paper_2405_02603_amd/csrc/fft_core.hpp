@@ -628,6 +628,62 @@ __device__ __forceinline__ void write_first_outputs(cx<T>* lds, const cx<T> (&v)
   }
 }
 
+// Exchange between the first stage (outputs of butterfly b at rows b R + m)
+// and the last stage of a two-stage plan (inputs of butterfly b2 at rows
+// b2 + r NB2) through an LDS array of real values: the real parts, then the
+// imaginary parts, so the array is half the size of a complex one.  The
+// caller has synchronised the array's previous use; three barriers inside.
+template <typename T, int R, int J, int NB, int NQ, int R2, int J2, int NB2, class IDX>
+__device__ __forceinline__ void exchange_split(T* lds, const cx<T> (&v)[J][R], cx<T> (&w)[J2][R2], int q,
+                                               IDX idx) {
+#pragma unroll
+  for (int part = 0; part < 2; ++part) {
+    if (part == 1) lds_barrier();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int b = q + NQ * j;
+      if ((NB % NQ == 0) || b < NB) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) lds[idx(b * R + m)] = part == 0 ? v[j][m].x : v[j][m].y;
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < J2; ++j) {
+      const int b = q + NQ * j;
+      if ((NB2 % NQ == 0) || b < NB2) {
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+          if (part == 0)
+            w[j][r].x = lds[idx(b + r * NB2)];
+          else
+            w[j][r].y = lds[idx(b + r * NB2)];
+        }
+      }
+    }
+  }
+}
+
+// The last stage on inputs already in registers (after exchange_split).
+template <typename T, int L, int PID, bool REV, int NQ, bool INV, bool HALF, int J, int R>
+__device__ __forceinline__ void last_stage_regs(cx<T> (&v)[J][R], const cx<T>* __restrict__ tw, int q) {
+  constexpr int S = plan_len(L, PID) - 1;
+  constexpr int NB = L / R;
+  static_assert(R == plan_radix(L, PID, REV, S), "register array matches the last radix");
+  static_assert(plan_ns(L, PID, REV, S) == NB, "last stage spans the pencil");
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int b = q + NQ * j;
+    if ((NB % NQ == 0) || b < NB) {
+      stage_twiddles<T, L, PID, REV, S, INV, false>(v[j], tw, b);
+      if constexpr (HALF)
+        dft_half_out<R, INV, T>(v[j]);
+      else
+        Dft<R, INV, T>::run(v[j]);
+    }
+  }
+}
+
 // Shape helpers for register arrays of the first / last stage.
 template <int L, int PID, bool REV, int NQ>
 struct FirstStage {

@@ -220,16 +220,22 @@ __global__ __launch_bounds__(TC* NQ) void k_col_fft(ColArgs a) {
 // rows k1 and 2 n1 - k1).  One item per launch; separate instantiations, so
 // the potential's kernel carries none of it.  With NOUT == 1 the spectrum is
 // not held through a loop (fewer registers).
-template <typename T, int L, int PID, int TC, int NQ, bool TWF = false, int NOUT = 0>
-__global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
+// SPLIT (two-stage plans): the exchanges go through a real-valued LDS array in
+// two rounds (real parts, then imaginary parts) with a padded row pitch, half
+// the LDS of a complex array, and the kernel is built for WPE waves per SIMD.
+template <typename T, int L, int PID, int TC, int NQ, bool TWF = false, int NOUT = 0, bool SPLIT = false, int WPE = 1>
+__global__ __launch_bounds__(TC* NQ, WPE) void k_col_conv(ColArgs a) {
   constexpr bool GRAD = NOUT > 0;
   constexpr int K = plan_len(L, PID);
   static_assert(!TWF || K > 1, "single-stage plans have no twiddles");
+  static_assert(!SPLIT || (K == 2 && !TWF), "split exchanges are built for two-stage plans without the table");
   // the others keep their registers for occupancy (at 1024 points the preloaded values spill)
-  constexpr bool PRE = K == 2 && !TWF && !GRAD && sizeof(T) == 4 && L <= 512;
+  constexpr bool PRE = K == 2 && !TWF && !GRAD && !SPLIT && sizeof(T) == 4 && L <= 512;
   constexpr int NT = TC * NQ;
   constexpr int TWN = TWF ? (twf_size(L, PID) + NT - 1) / NT : 1;  // table entries per thread
-  __shared__ cx<T> lds[K > 1 ? L * TC : 1];
+  constexpr int SP = TC + 1;  // split row pitch: rows R apart fall in other banks
+  __shared__ cx<T> lds[K > 1 && !SPLIT ? L * TC : 1];
+  __shared__ T ldss[SPLIT ? L * SP : 1];
   __shared__ cx<T> twl[TWF ? twf_size(L, PID) : 1];
   const int tid = threadIdx.x;
   const int c = tid % TC, q = tid / TC;
@@ -254,6 +260,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(a.tw);
   const unsigned rs = (unsigned)a.row_stride;  // row offsets of one pencil fit in 32 bits (unsigned: no sign extension)
   auto idx = [c](int row) { return row * TC + c; };
+  auto idxs = [c](int row) { return row * SP + c; };
   using F = FirstStage<L, PID, false, NQ>;   // forward, first stage
   using Lf = LastStage<L, PID, false, NQ>;   // forward, last stage == inverse, first stage
   using Li = LastStage<L, PID, true, NQ>;    // inverse, last stage
@@ -366,12 +373,17 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
         }
       }
     } else {
-      lds_barrier();
-      write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, x, q, idx);
-      lds_barrier();
-      lds_stages<T, L, PID, true, 1, K - 1, NQ, true, TWF>(lds, tws, q, idx);
       cx<T> u[Li::J][Li::R];
-      lds_last_stage<T, L, PID, true, NQ, true, TWF, true>(lds, tws, q, idx, u);
+      lds_barrier();
+      if constexpr (SPLIT) {
+        exchange_split<T, Lf::R, Lf::J, Lf::NB, NQ, Li::R, Li::J, Li::NB>(ldss, x, u, q, idxs);
+        last_stage_regs<T, L, PID, true, NQ, true, true>(u, tws, q);
+      } else {
+        write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, x, q, idx);
+        lds_barrier();
+        lds_stages<T, L, PID, true, 1, K - 1, NQ, true, TWF>(lds, tws, q, idx);
+        lds_last_stage<T, L, PID, true, NQ, true, TWF, true>(lds, tws, q, idx, u);
+      }
 #pragma unroll
       for (int j = 0; j < Li::J; ++j) {
         const int b = q + NQ * j;
@@ -400,6 +412,9 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
       for (int j = 0; j < Lf::J; ++j)
 #pragma unroll
         for (int m = 0; m < Lf::R; ++m) w[j][m] = v[j][m];
+    } else if constexpr (SPLIT) {
+      exchange_split<T, F::R, F::J, F::NB, NQ, Lf::R, Lf::J, Lf::NB>(ldss, v, w, q, idxs);
+      last_stage_regs<T, L, PID, false, NQ, false, false>(w, tws, q);
     } else {
       write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
       lds_barrier();
@@ -440,7 +455,7 @@ __global__ __launch_bounds__(TC* NQ) void k_col_conv(ColArgs a) {
   };
   // GRAD where registers are short (long pencils per thread): the second set
   // is read after the first set's outputs, not held through them
-  constexpr bool LATE_B = NOUT > 1 && sizeof(T) * L / NQ >= 128;
+  constexpr bool LATE_B = (NOUT > 1 && sizeof(T) * L / NQ >= 128) || (SPLIT && WPE >= 3);
   cx<T> raw_a[F::J][F::R / 2], raw_b[F::J][F::R / 2];
   issue_fence();
   load_set(data + off_a, true, raw_a);

@@ -85,7 +85,8 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
   }
 }
 
-// Axis-0 pass variants: variants 0 and 1 as col_cfg; variant 2 keeps the
+// Axis-0 pass variants: variant 0 as col_cfg, variant 1 as col_cfg or the
+// split-exchange form (conv_split_wpe, below); variant 2 keeps the
 // complete twiddle table in LDS, with the shape of variant 0 (else 1) when the
 // table costs no resident block (conv_twf_fits), else it is the pipelined
 // persistent kernel (grid of at most CONV_PIPE_BLOCKS blocks) with the shape
@@ -114,11 +115,22 @@ __host__ __device__ constexpr bool conv_pipelined(int L, int v) {
   return v == 2 && !conv_twf<T>(L, v) && L >= 128 && plan_len(L, col_cfg<T>(L, 1).pid) > 1;
 }
 
+// Axis-0 pass variant 1 where conv_split_wpe(L) > 0: the shape of variant 0
+// (a two-stage plan) with the exchange between its stages made through a real
+// LDS array in two rounds, real parts then imaginary parts (half the LDS of a
+// block), and the kernel built for that many waves per SIMD, so that more
+// blocks share a compute unit.  Elsewhere variant 1 is col_cfg's.
+template <typename T>
+__host__ __device__ constexpr int conv_split_wpe(int L) {
+  return sizeof(T) == 4 && L == 512 ? 3 : 0;
+}
+
 template <typename T>
 __host__ __device__ constexpr TileCfg conv_cfg(int L, int v) {
   return conv_twf<T>(L, v) ? col_cfg<T>(L, conv_twf_fits<T>(L, 0) ? 0 : 1)
-         : conv_pipelined<T>(L, v) ? col_cfg<T>(L, 1)
-                                   : col_cfg<T>(L, v);
+         : conv_pipelined<T>(L, v)                ? col_cfg<T>(L, 1)
+         : v == 1 && conv_split_wpe<T>(L) > 0     ? col_cfg<T>(L, 0)
+                                                  : col_cfg<T>(L, v);
 }
 
 #define FSP_ROW_LENGTHS(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
@@ -240,6 +252,10 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
         if constexpr (conv_twf<T>(LV, VV))                                                          \
           hipLaunchKernelGGL((k_col_conv<T, LV, cc.pid, cc.tiles, cc.nq, true>), gridc,             \
                              dim3(cc.tiles * cc.nq), 0, s, b);                                      \
+        else if constexpr (VV == 1 && conv_split_wpe<T>(LV) > 0)                                    \
+          hipLaunchKernelGGL((k_col_conv<T, LV, cc.pid, cc.tiles, cc.nq, false, 0, true,            \
+                                         conv_split_wpe<T>(LV)>),                                   \
+                             gridc, dim3(cc.tiles * cc.nq), 0, s, b);                               \
         else                                                                                        \
           hipLaunchKernelGGL((k_col_conv<T, LV, cc.pid, cc.tiles, cc.nq>), gridc,                   \
                              dim3(cc.tiles * cc.nq), 0, s, b);                                      \
