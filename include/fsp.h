@@ -210,6 +210,15 @@ fsp_status fsp_solve_grad(fsp_plan p, const void* rho, void* phi, void* grad, vo
  * in float64): one kernel holds a column tile's whole (axis 0, axis 1) slab in
  * LDS and runs passes 1-3 there; fsp_solve_passes then accepts only ranges
  * that contain all of 1-3 or none of them (FSP_ERR_INVALID_ARG otherwise).
+ * The value 4 in variants[0] and variants[1] (both) selects the plane kernel
+ * for passes 0-1, and in variants[3] and variants[4] (both) the one for passes
+ * 3-4, on grids with n1 == n2 whose i0-plane of the axis-2 spectrum fits in
+ * LDS (n1 in {32, 48, 64, 96, 128} in float32, {32, 48, 64} in float64): one
+ * block per plane runs the axis-2 and the axis-1 transforms with the plane
+ * held in LDS, so the axis-2 spectrum never goes to device memory;
+ * fsp_solve_passes then accepts only ranges that contain both passes of such
+ * a pair or neither (FSP_ERR_INVALID_ARG otherwise).  The plane pairs and the
+ * fused schedule exclude each other.
  * Results are identical up to rounding order across schedules.  A new plan starts with the schedule last tuned for its grid and
  * precision in this process (else all zeros). */
 fsp_status fsp_plan_get_schedule(fsp_plan p, int* variants /* [5] */);
@@ -224,10 +233,12 @@ fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants /* [5] */);
  * device arrays as in fsp_solve, but phi must not overlap rho
  * (FSP_ERR_INVALID_ARG): the timed solves write phi many times.  On
  * return phi holds the solve of rho with the tuned schedule.  Synchronises
- * `stream`.  times_ms (NULL or [5 * 3 + 2]) receives the median time of each
- * variant, times_ms[pass * 3 + variant], then the time of passes 1-3 fused and
- * of passes 1-3 with the best separate variants (0 when fusion is not
- * supported); the fused schedule is kept when it is faster.  On a plan with
+ * `stream`.  times_ms (NULL or [5 * 3 + 5]) receives the median time of each
+ * variant, times_ms[pass * 3 + variant], then the median time of whole solves
+ * with schedules built from the best variants: times_ms[15] passes 1-3 fused,
+ * [16] all passes separate, [17] both plane pairs (0-1 and 3-4), [18] the
+ * plane pair 0-1 alone, [19] the pair 3-4 alone (0 where the schedule is not
+ * supported); the fastest of these schedules is kept.  On a plan with
  * FSP_WANT_GRAD it also times the gradient solve's axis-0 pass (four outputs)
  * in each of its variants and keeps the fastest for fsp_solve_grad
  * (fsp_plan_set_schedule drops that choice: the gradient then follows the
@@ -311,7 +322,8 @@ fsp_status fsp_plan_ghat_layout(fsp_plan p, size_t* octant_offset, int* tile);
 fsp_status fsp_plan_octant_offset(fsp_plan p, int component, size_t* offset);
 
 /* Model bytes that one solve moves through HBM with this plan's schedule
- * (reads + writes of the five passes, the Green's octant included): the
+ * (reads + writes of its kernels, the Green's octant included: five passes,
+ * fewer where the fused slab or a plane pair keeps intermediates in LDS): the
  * memory traffic against which Section 3.4 finds the solve memory-bound. */
 fsp_status fsp_plan_model_bytes(fsp_plan p, double* bytes);
 

@@ -259,14 +259,16 @@ class Plan:
         if out is None:
             out = torch.empty_like(rho)
         self._check_field(out, "out")
-        times = (ctypes.c_float * (5 * _lib.NUM_VARIANTS + 2))()
+        times = (ctypes.c_float * (5 * _lib.NUM_VARIANTS + 5))()
         with torch.cuda.device(self.device):
             check(self._lib.fsp_autotune(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                          int(reps), _stream_ptr(stream), times), "fsp_autotune")
         nv = _lib.NUM_VARIANTS
         out = {p: [times[p * nv + v] for v in range(nv)] for p in range(5)}
-        out["fused_1_3"] = times[5 * nv]
-        out["separate_1_3"] = times[5 * nv + 1]
+        # whole solves with schedules built from the best variants (0: not supported)
+        for i, key in enumerate(("solve_fused", "solve_separate", "solve_plane", "solve_plane_fwd",
+                                 "solve_plane_inv")):
+            out[key] = times[5 * nv + i]
         return out
 
     @property

@@ -23,6 +23,7 @@ FSP_ERR_DEVICE = 6
 GREENS = {"hockney": 0, "vico": 1, "vico_dct": 2}
 NUM_VARIANTS = 3
 FUSED = 3  # schedule value of passes 1-3 selecting the fused small-grid kernel
+PLANE = 4  # schedule value of passes 0-1 (both) or 3-4 (both) selecting the plane kernels
 FSP_WANT_GRAD = 1  # plan flag: derivative tables and a workspace for fsp_solve_grad
 FSP_PERIODIC = (2, 4, 8)  # plan flags: axis 0, 1, 2 periodic
 PREC = {"f32": 0, "f64": 1}

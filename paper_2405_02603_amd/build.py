@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "libfsp.so")
 ARCH = os.environ.get("FSP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "serve_engine.hip", "greens.hip", "solve_f32.hip", "solve_f64.hip", "solve_rows_f32.hip", "solve_rows_f64.hip",
-           "solve_cols_f32.hip", "solve_cols_f64.hip"]
+           "solve_cols_f32.hip", "solve_cols_f64.hip", "solve_plane_f32.hip", "solve_plane_f64.hip"]
 
 
 def hipcc() -> str:

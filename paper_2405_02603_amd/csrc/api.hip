@@ -329,13 +329,17 @@ std::map<TuneKey, std::array<int, 6>> g_tuned;  // schedule, then the gradient's
 double model_bytes(const fsp_plan_s* p) {
   // P1 reads rho, writes (n2+1) n1 n0 complex; P2 reads that, writes 2 n1 (n2+1) n0;
   // P3 reads/writes 2 n1 (n2+1) n0 and reads the octant; P4 mirrors P2, P5 mirrors P1.
+  // The fused slab (passes 1-3) reads and writes the (n2+1) n1 n0 rows once; a
+  // plane pair reads rho and writes S (0-1), or reads S and writes phi (3-4).
   const double n0 = p->n[0], n1 = p->n[1], n2 = p->n[2], s = p->rb;
   const double real_grid = n0 * n1 * n2;
   const double half1 = n0 * n1 * (n2 + 1) * 2;      // reals in (n2+1) n1 n0 complex
   const double half2 = n0 * 2 * n1 * (n2 + 1) * 2;  // reals in 2 n1 (n2+1) n0 complex
   const double octant = (n0 + 1) * (n1 + 1) * (n2 + 1);
-  const double reals = 2 * real_grid + 2 * half1 + 2 * (half1 + half2) + 2 * half2 + octant;
-  return reals * s;
+  if (p->var[1] == fsp::FUSED) return (2 * real_grid + 4 * half1 + octant) * s;
+  const double fwd = p->var[0] == fsp::PLANE ? real_grid + half2 : real_grid + 2 * half1 + half2;
+  const double inv = p->var[3] == fsp::PLANE ? real_grid + half2 : real_grid + 2 * half1 + half2;
+  return (fwd + 2 * half2 + octant + inv) * s;
 }
 
 }  // namespace
@@ -798,12 +802,15 @@ static fsp::SolveGeom group_geom(const fsp_plan_s* p, const int* var) {
   for (int i = 0; i < 5; ++i) g.var[i] = var[i];
   // the radix plan of a variant may differ between the precisions
   const bool f64 = p->d.prec == FSP_F64;
-  const int pr1 = f64 ? fsp::row_cfg<double>(p->n[2], var[0]).pid : fsp::row_cfg<float>(p->n[2], var[0]).pid;
-  const int pr5 = f64 ? fsp::row_cfg<double>(p->n[2], var[4]).pid : fsp::row_cfg<float>(p->n[2], var[4]).pid;
+  const fsp::PlaneCfg pcf = f64 ? fsp::plane_cfg<double>(p->n[2]) : fsp::plane_cfg<float>(p->n[2]);
+  const bool plane_fwd = var[0] == fsp::PLANE, plane_inv = var[3] == fsp::PLANE;
+  auto row_pid = [&](int v) { return f64 ? fsp::row_cfg<double>(p->n[2], v).pid : fsp::row_cfg<float>(p->n[2], v).pid; };
+  const int pr1 = plane_fwd ? pcf.pidr : row_pid(var[0]);
+  const int pr5 = plane_inv ? pcf.pidr : row_pid(var[4]);
   const bool fused = var[1] == fsp::FUSED;
   auto col_pid = [&](int L, int v) { return f64 ? fsp::col_cfg<double>(L, v).pid : fsp::col_cfg<float>(L, v).pid; };
-  const int pc2 = fused ? 0 : col_pid(2 * p->n[1], var[1]);
-  const int pc4 = fused ? 0 : col_pid(2 * p->n[1], var[3]);
+  const int pc2 = fused ? 0 : plane_fwd ? pcf.pidc : col_pid(2 * p->n[1], var[1]);
+  const int pc4 = fused ? 0 : plane_inv ? pcf.pidc : col_pid(2 * p->n[1], var[3]);
   const int pc3 = fused ? 0
                   : f64 ? fsp::conv_cfg<double>(2 * p->n[0], var[2]).pid
                         : fsp::conv_cfg<float>(2 * p->n[0], var[2]).pid;
@@ -974,6 +981,10 @@ fsp_status fsp_solve_passes(fsp_plan p, const void* rho, void* phi, int first, i
   if ((first == 0 && !rho) || (last == 4 && !phi)) return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: NULL rho/phi for its pass");
   if (p->var[1] == fsp::FUSED && first <= 3 && last >= 1 && (first > 1 || last < 3))
     return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: the fused schedule runs passes 1-3 together");
+  if (p->var[0] == fsp::PLANE && (first == 1 || (first == 0 && last == 0)))
+    return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: the plane schedule runs passes 0-1 together");
+  if (p->var[3] == fsp::PLANE && (first == 4 || (first <= 3 && last == 3)))
+    return fail(FSP_ERR_INVALID_ARG, "fsp_solve_passes: the plane schedule runs passes 3-4 together");
   if (!p->ready) return fail(FSP_ERR_NOT_READY, "fsp_solve_passes: plan has no bound buffers or no precomputed transform");
   DeviceGuard guard;
   hipError_t e = guard.enter(p->device);
@@ -1046,15 +1057,28 @@ static bool fused_supported(const fsp_plan_s* p) {
                               : fsp::slab_cfg<float>(2 * p->n[1]).tiles > 0;
 }
 
+static bool plane_supported(const fsp_plan_s* p) {
+  if (p->n[1] != p->n[2] || p->chunks != 1) return false;
+  return p->d.prec == FSP_F64 ? fsp::plane_cfg<double>(p->n[2]).tc > 0 : fsp::plane_cfg<float>(p->n[2]).tc > 0;
+}
+
 fsp_status fsp_plan_set_schedule(fsp_plan p, const int* variants) {
   if (!p || !variants) return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: NULL argument");
   const bool fused = variants[1] == fsp::FUSED;
   if (fused && (variants[2] != fsp::FUSED || variants[3] != fsp::FUSED || !fused_supported(p)))
     return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: the fused schedule needs passes 1-3 all set to 3, "
                                      "n0 == n1 and a grid small enough for the slab to fit in LDS");
+  const bool plane_fwd = variants[0] == fsp::PLANE || variants[1] == fsp::PLANE;
+  const bool plane_inv = variants[3] == fsp::PLANE || variants[4] == fsp::PLANE;
+  if ((plane_fwd && (variants[0] != fsp::PLANE || variants[1] != fsp::PLANE)) ||
+      (plane_inv && (variants[3] != fsp::PLANE || variants[4] != fsp::PLANE)) ||
+      ((plane_fwd || plane_inv) && !plane_supported(p)))
+    return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: the plane schedule needs passes 0 and 1 (or 3 and 4) "
+                                     "both set to 4, n1 == n2 and a plane that fits in LDS");
   for (int i = 0; i < 5; ++i) {
     const bool mid = i >= 1 && i <= 3;
-    if (variants[i] < 0 || (variants[i] >= fsp::NUM_VARIANTS && !(mid && fused)))
+    const bool in_plane = (i <= 1 && plane_fwd) || (i >= 3 && plane_inv);
+    if (variants[i] < 0 || (variants[i] >= fsp::NUM_VARIANTS && !(mid && fused) && !in_plane))
       return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: variant out of range");
     if (mid && !fused && variants[i] == fsp::FUSED)
       return fail(FSP_ERR_INVALID_ARG, "fsp_plan_set_schedule: variant out of range");
@@ -1090,6 +1114,8 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
   int best[5];
   for (int i = 0; i < 5; ++i) best[i] = p->var[i];
   if (best[1] == fsp::FUSED) best[1] = best[2] = best[3] = 0;  // tune the separate passes first
+  if (best[0] == fsp::PLANE) best[0] = best[1] = 0;
+  if (best[3] == fsp::PLANE) best[3] = best[4] = 0;
   // Each variant is timed inside full solves (the pass reads what the pass
   // before it just wrote, as in a real solve): events around the pass only.
   for (int pass = 0; pass < 5 && e == hipSuccess; ++pass) {
@@ -1123,19 +1149,19 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
       }
     }
   }
-  // the fused passes 1-3, against the sum of the best separate ones
-  if (e == hipSuccess && fused_supported(p)) {
-    fsp_status st_range = FSP_OK;
-    auto time_range = [&](const int* sched, float* out) -> hipError_t {
+  // whole-solve schedules built from the best separate variants: the separate
+  // passes, the fused slab (passes 1-3), the plane kernels for passes 0-1 and
+  // 3-4 (both pairs, or either alone); each timed as a full solve, the fastest kept
+  if (e == hipSuccess) {
+    fsp_status st_sched = FSP_OK;
+    auto time_solve = [&](const int* sched, float* out) -> hipError_t {
       for (int i = 0; i < 5; ++i) p->var[i] = sched[i];
       hipError_t r = hipSuccess;
       float rep_ms[8] = {};
       for (int k = 0; k <= reps && r == hipSuccess; ++k) {
-        if ((st_range = solve_one(p, rho, phi, s, 0, 0)) != FSP_OK) return hipErrorInvalidValue;
         r = hipEventRecord(e0, s);
-        if (r == hipSuccess && (st_range = solve_one(p, rho, phi, s, 1, 3)) != FSP_OK) return hipErrorInvalidValue;
+        if (r == hipSuccess && (st_sched = solve_one(p, rho, phi, s)) != FSP_OK) return hipErrorInvalidValue;
         if (r == hipSuccess) r = hipEventRecord(e1, s);
-        if (r == hipSuccess && (st_range = solve_one(p, rho, phi, s, 4, 4)) != FSP_OK) return hipErrorInvalidValue;
         if (r == hipSuccess) r = hipEventSynchronize(e1);
         float ms = 0;
         if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
@@ -1144,21 +1170,33 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
       *out = median_ms(rep_ms, reps);
       return r;
     };
-    int fused[5] = {best[0], fsp::FUSED, fsp::FUSED, fsp::FUSED, best[4]};
-    float t_sep = 0, t_fused = 0;
-    e = time_range(best, &t_sep);
-    if (e == hipSuccess) e = time_range(fused, &t_fused);
-    if (times_ms) times_ms[5 * fsp::NUM_VARIANTS] = t_fused, times_ms[5 * fsp::NUM_VARIANTS + 1] = t_sep;
-    if (st_range != FSP_OK) {
-      for (int i = 0; i < 5; ++i) p->var[i] = best[i];
-      if (e0) (void)hipEventDestroy(e0);
-      if (e1) (void)hipEventDestroy(e1);
-      return st_range;
+    const int P = fsp::PLANE, Fu = fsp::FUSED;
+    const int cand[5][5] = {{best[0], best[1], best[2], best[3], best[4]},
+                            {best[0], Fu, Fu, Fu, best[4]},
+                            {P, P, best[2], P, P},
+                            {P, P, best[2], best[3], best[4]},
+                            {best[0], best[1], best[2], P, P}};
+    const bool ok[5] = {true, fused_supported(p), plane_supported(p), plane_supported(p), plane_supported(p)};
+    float t[5] = {0, 0, 0, 0, 0};
+    int pick = 0;
+    for (int c = 0; c < 5 && e == hipSuccess; ++c) {
+      if (!ok[c]) continue;
+      e = time_solve(cand[c], &t[c]);
+      if (st_sched != FSP_OK) {
+        for (int i = 0; i < 5; ++i) p->var[i] = best[i];
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return st_sched;
+      }
+      if (e == hipSuccess && t[c] < t[pick]) pick = c;
     }
-    if (e == hipSuccess && t_fused < t_sep)
-      for (int i = 1; i <= 3; ++i) best[i] = fsp::FUSED;
-  } else if (times_ms) {
-    times_ms[5 * fsp::NUM_VARIANTS] = times_ms[5 * fsp::NUM_VARIANTS + 1] = 0.0f;
+    if (times_ms) {
+      times_ms[5 * fsp::NUM_VARIANTS] = t[1];
+      times_ms[5 * fsp::NUM_VARIANTS + 1] = t[0];
+      for (int c = 2; c < 5; ++c) times_ms[5 * fsp::NUM_VARIANTS + c] = t[c];
+    }
+    if (e == hipSuccess)
+      for (int i = 0; i < 5; ++i) best[i] = cand[pick][i];
   }
   for (int i = 0; i < 5; ++i) p->var[i] = best[i];
   // the gradient solve's axis-0 pass (four outputs), each of its variants

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "solve_kernels.hpp"
+#include "plane_kernels.hpp"
 
 namespace fsp {
 
@@ -278,6 +279,9 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
 // one block per TC columns holds the (i0, k1) slab in LDS.  tiles == 0 means
 // unsupported.  LDS = (n N TC + groups TC 2n) sizeof(cx<T>) <= 160 KB.
 constexpr int FUSED = 3;  // schedule value of passes 1..3 selecting the fused kernel
+// Schedule value of passes 0 and 1 (both) or 3 and 4 (both) selecting the
+// plane kernels (plane_kernels.hpp) for that pair.
+constexpr int PLANE = 4;
 
 template <typename T>
 __host__ __device__ constexpr TileCfg slab_cfg(int L) {
@@ -325,6 +329,8 @@ extern template hipError_t launch_p5<double>(int, int, const RowArgs&, int, hipS
 extern template hipError_t launch_col<double>(int, int, int, const ColArgs&, int, hipStream_t);
 extern template hipError_t launch_slab<float>(int, const SlabArgs&, int, hipStream_t);
 extern template hipError_t launch_slab<double>(int, const SlabArgs&, int, hipStream_t);
+extern template hipError_t launch_plane<float>(int, int, bool, const PlaneArgs&, int, hipStream_t);
+extern template hipError_t launch_plane<double>(int, int, bool, const PlaneArgs&, int, hipStream_t);
 #endif
 
 // Geometry of up to MAX_ITEMS solves of one shape, filled by the plans.
@@ -416,7 +422,32 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
     c.ncols = c1;
     c.ntiles = (c1 - c0 + tcw - 1) / tcw;
   };
+  // passes 0-1 / 3-4 as the plane kernels: the pair runs at its first pass
+  const bool plane_fwd = g.var[0] == PLANE, plane_inv = g.var[3] == PLANE;
+  PlaneArgs pa{};
+  pa.items = g.items_dev;
+  pa.plane = plane;
+  pa.pitch = g.pitch;
   auto run = [&](int pass, int c0, int c1) -> hipError_t {
+    if ((pass == 1 && plane_fwd) || (pass == 4 && plane_inv)) return hipSuccess;
+    if (pass == 0 && plane_fwd) {
+      for (int i = 0; i < nfill; ++i) {
+        pa.in[i] = g.rho[i];
+        pa.out[i] = g.work[i];
+      }
+      pa.twr = g.tw_row[0];
+      pa.twc = g.tw_c1[1];
+      return launch_plane<T>(g.n2, g.n0, false, pa, g.items, s);
+    }
+    if (pass == 3 && plane_inv) {
+      for (int i = 0; i < (tab ? 0 : npost); ++i) {
+        pa.in[i] = after[i];
+        pa.out[i] = result[i];
+      }
+      pa.twr = g.tw_row[4];
+      pa.twc = g.tw_c1[3];
+      return launch_plane<T>(g.n2, g.n0, true, pa, npost, s);
+    }
     switch (pass) {
       case 0:
         for (int i = 0; i < nfill; ++i) {
@@ -464,6 +495,11 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
   hipError_t e = hipSuccess;
   if (g.nout < 0 || g.nout > MAX_OUT || (g.nout && (g.items != 1 || g.var[1] == FUSED)))
     return hipErrorInvalidValue;  // one item, separate passes: the caller picks them
+  // a plane pair is one kernel: a range holds both of its passes or neither
+  if ((plane_fwd && (g.var[1] != PLANE || (first == 1 && last >= 1) || (first == 0 && last == 0))) ||
+      (plane_inv && (g.var[4] != PLANE || (first <= 3 && last == 3) || (first == 4))) ||
+      ((plane_fwd || plane_inv) && (g.n1 != g.n2 || g.chunks > 1 || g.var[1] == FUSED)))
+    return hipErrorInvalidValue;
   if (g.var[1] == FUSED) {
     // passes 1-3 as one fused kernel over column tiles: a range holds all of
     // them or none (pass 0 or pass 4 alone)

@@ -166,6 +166,47 @@ def test_schedule_validation(lib):
     lib.fsp_plan_destroy(h)
 
 
+@pytest.mark.parametrize("prec,n,supported", [(0, 32, True), (0, (16, 96, 96), True),
+                                              (0, 128, True), (0, 256, False),
+                                              (0, (32, 32, 64), False), (0, 24, False),
+                                              (1, 64, True), (1, 96, False)])
+def test_plane_schedule_validation(lib, prec, n, supported):
+    """The plane pairs: passes 0 and 1 (or 3 and 4) both set to 4, on grids with n1 == n2 whose
+    plane fits in LDS; a pass range holds both passes of a pair or neither; the pairs exclude the
+    fused slab schedule."""
+    st, h = _create(lib, _desc(n=n, prec=prec, greens=0))
+    assert st == _lib.FSP_OK
+    P, F = _lib.PLANE, _lib.FUSED
+    want = _lib.FSP_OK if supported else _lib.FSP_ERR_INVALID_ARG
+    for sched in ((P, P, 0, P, P), (P, P, 2, 1, 0), (1, 2, 0, P, P)):
+        assert lib.fsp_plan_set_schedule(h, (ctypes.c_int * 5)(*sched)) == want, sched
+    for bad in ((P, 0, 0, 0, 0), (0, P, 0, 0, 0), (0, 0, 0, P, 0), (0, 0, 0, 0, P), (0, 0, P, 0, 0),
+                (P, P, F, F, F), (0, F, F, F, P), (P, P, 3, P, P)):
+        assert lib.fsp_plan_set_schedule(h, (ctypes.c_int * 5)(*bad)) == _lib.FSP_ERR_INVALID_ARG, bad
+    if supported:
+        # model bytes follow the schedule: each plane pair saves a write and a read of the
+        # (n2+1) n1 n0 axis-2 spectrum
+        n3 = n if isinstance(n, tuple) else (n,) * 3
+        rb = 4 if prec == 0 else 8
+        half1 = n3[0] * n3[1] * (n3[2] + 1) * 2 * rb
+        mb = ctypes.c_double()
+        assert lib.fsp_plan_set_schedule(h, (ctypes.c_int * 5)(0, 0, 0, 0, 0)) == _lib.FSP_OK
+        assert lib.fsp_plan_model_bytes(h, ctypes.byref(mb)) == _lib.FSP_OK
+        sep = mb.value
+        assert lib.fsp_plan_set_schedule(h, (ctypes.c_int * 5)(P, P, 0, 0, 0)) == _lib.FSP_OK
+        assert lib.fsp_plan_model_bytes(h, ctypes.byref(mb)) == _lib.FSP_OK
+        assert mb.value == sep - 2 * half1
+        assert lib.fsp_plan_set_schedule(h, (ctypes.c_int * 5)(P, P, 0, P, P)) == _lib.FSP_OK
+        assert lib.fsp_plan_model_bytes(h, ctypes.byref(mb)) == _lib.FSP_OK
+        assert mb.value == sep - 4 * half1
+        dummy = ctypes.c_void_p(256)
+        for first, last in ((0, 0), (1, 1), (1, 2), (3, 3), (4, 4), (2, 3), (1, 4)):
+            assert lib.fsp_solve_passes(h, dummy, dummy, first, last, None) == _lib.FSP_ERR_INVALID_ARG, (first, last)
+        for first, last in ((0, 1), (2, 2), (3, 4), (0, 4), (0, 2), (2, 4)):
+            assert lib.fsp_solve_passes(h, dummy, dummy, first, last, None) == _lib.FSP_ERR_NOT_READY, (first, last)
+    lib.fsp_plan_destroy(h)
+
+
 def test_gradient_plan_sizes_offsets_and_errors(lib):
     # unknown flag bits are rejected (bits 1-3 are the periodic axes)
     d = _desc(n=32)

@@ -90,6 +90,9 @@ def test_gradient_vs_oracle_every_schedule(torch_cuda, kind, prec, tol):
         scheds = [[v] * 5 for v in range(_lib.NUM_VARIANTS)]
         if n3[0] == n3[1] and n3[0] <= 48:
             scheds.append([0, _lib.FUSED, _lib.FUSED, _lib.FUSED, 0])   # passes 1-3 run separately here
+        if n3[1] == n3[2] and n3[2] in ((32, 48, 64, 96, 128) if prec == "f32" else (32, 48, 64)):
+            P = _lib.PLANE   # the plane kernels: passes 3-4 take the four outputs as items
+            scheds += [[P, P, 0, P, P], [P, P, 1, 0, 0], [0, 0, 2, P, P]]
         for sched in scheds:
             plan.schedule = sched
             grad, phi = plan.solve_grad(r, want_phi=True)

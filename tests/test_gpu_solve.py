@@ -154,7 +154,8 @@ def test_autotune_256(torch_cuda, prec):
     times = plan.autotune(r, reps=2)
     torch.cuda.synchronize()
     assert all(t > 0 for p in range(5) for t in times[p])
-    assert times["fused_1_3"] == 0.0          # 256^3 is too large for the fused slab schedule
+    assert times["solve_fused"] == 0.0        # 256^3 is too large for the fused slab schedule
+    assert times["solve_plane"] == 0.0        # and for the plane kernels
     sched = plan.schedule
     for p in range(5):
         assert times[p][sched[p]] == min(times[p])
@@ -210,9 +211,10 @@ def test_fused_schedule_in_batch_and_anisotropic_n2(torch_cuda):
 
 @pytest.mark.parametrize("prec,n", [("f32", 32), ("f32", 64), ("f64", 32), ("f64", 48)])
 def test_autotune_fused_sizes(torch_cuda, prec, n):
-    """On grids small enough for the fused schedule the autotuner also times passes 1-3
-    fused against the best separate ones (pass 0 and pass 4 are then run on their own);
-    whatever it keeps matches the oracle, and so does a solve split into pass ranges."""
+    """On grids small enough for the fused schedule and the plane kernels the autotuner also
+    times whole solves with passes 1-3 fused and with the plane pairs, against the best separate
+    passes, and keeps the fastest; whatever it keeps matches the oracle, and so does a solve split
+    into pass ranges."""
     from paper_2405_02603_amd import _lib
     torch = torch_cuda
     lo, hi = (-1.0,) * 3, (1.0,) * 3
@@ -224,8 +226,13 @@ def test_autotune_fused_sizes(torch_cuda, prec, n):
     r = to_dev(rho, dt)
     times = plan.autotune(r, reps=2)
     torch.cuda.synchronize()
-    assert times["fused_1_3"] > 0 and times["separate_1_3"] > 0
-    assert (plan.schedule[1] == _lib.FUSED) == (times["fused_1_3"] < times["separate_1_3"])
+    keys = ("solve_separate", "solve_fused", "solve_plane", "solve_plane_fwd", "solve_plane_inv")
+    assert all(times[k] > 0 for k in keys)
+    P, F = _lib.PLANE, _lib.FUSED
+    sched = plan.schedule
+    kept = ("solve_fused" if sched[1] == F else "solve_plane" if sched[0] == P and sched[3] == P
+            else "solve_plane_fwd" if sched[0] == P else "solve_plane_inv" if sched[3] == P else "solve_separate")
+    assert times[kept] == min(times[k] for k in keys), (sched, times)
     assert rel_l2(to_host(plan.solve(r)), ref) <= tol
     plan.schedule = [0, _lib.FUSED, _lib.FUSED, _lib.FUSED, 0]
     phi = torch.empty_like(r)
@@ -234,6 +241,70 @@ def test_autotune_fused_sizes(torch_cuda, prec, n):
     plan.solve_passes(None, phi, 4, 4)
     torch.cuda.synchronize()
     assert rel_l2(to_host(phi), ref) <= tol
+
+
+@pytest.mark.parametrize("prec,tol,etol,sizes", [
+    ("f32", F32_TOL, F32_ELEM, (32, 48, 64, 96, 128, (24, 64, 64))),
+    ("f64", F64_TOL, F64_ELEM, (32, 48, 64, (16, 48, 48)))])
+def test_plane_schedule(torch_cuda, prec, tol, etol, sizes):
+    """Passes 0-1 and 3-4 as the plane kernels (the axis-2 spectrum of one i0-plane held in LDS
+    between the axis-2 and axis-1 transforms) give the oracle's result element by element, for
+    both kernels, with both pairs and with each alone, and a solve split into pass ranges at the
+    pairs' boundaries gives the same."""
+    from paper_2405_02603_amd import _lib
+    torch = torch_cuda
+    P = _lib.PLANE
+    dt = torch.float64 if prec == "f64" else torch.float32
+    for n in sizes:
+        n3 = W._as3(n, int)
+        for kind in ("hockney", "vico_dct"):
+            lo, hi = (-1.0, -1.0, -0.5), (1.0, 1.0, 1.5)
+            rho = W.random_field(n3, 40 + n3[0])
+            ref = reference(rho, kind, lo, hi, use_direct=False)
+            plan = _plan(n3, lo, hi, kind, prec)
+            r = to_dev(rho, dt)
+            for sched in ([P, P, 0, P, P], [P, P, 1, 0, 2], [2, 1, 2, P, P]):
+                plan.schedule = sched
+                phi = to_host(plan.solve(r))
+                torch.cuda.synchronize()
+                assert rel_l2(phi, ref) <= tol, (n, kind, sched)
+                assert elem_err(phi, ref) <= etol, (n, kind, sched)
+            plan.schedule = [P, P, 0, P, P]
+            out = torch.empty_like(r)
+            plan.solve_passes(r, None, 0, 1)
+            plan.solve_passes(None, None, 2, 2)
+            plan.solve_passes(None, out, 3, 4)
+            torch.cuda.synchronize()
+            assert elem_err(to_host(out), ref) <= etol, (n, kind, "ranges")
+
+
+def test_plane_schedule_batched_and_in_place(torch_cuda):
+    """Plane plans in a batched launch (several items in one plane launch, with a separate-pass
+    plan of another shape beside them) equal their solo solves bit for bit and the oracle; an
+    in-place plane solve (phi == rho) is correct too."""
+    from paper_2405_02603_amd import _lib, solve_batched
+    torch = torch_cuda
+    P = _lib.PLANE
+    plans, rhos, refs = [], [], []
+    for i, n in enumerate([(48, 48, 48), (48, 48, 48), (48, 48, 48), (32, 32, 32)]):
+        lo, hi = (-1.0,) * 3, (1.0,) * 3
+        rho = W.random_field(n, 60 + i)
+        p = _plan(n, lo, hi, "vico_dct", "f32")
+        p.schedule = [P, P, 0, P, P] if n[0] == 48 else [0, 0, 0, 0, 0]
+        plans.append(p)
+        rhos.append(to_dev(rho, torch.float32))
+        refs.append(reference(rho, "vico_dct", lo, hi, use_direct=False))
+    outs = solve_batched(plans, rhos)
+    torch.cuda.synchronize()
+    for p, r, o, ref in zip(plans, rhos, outs, refs):
+        solo = p.solve(r)
+        torch.cuda.synchronize()
+        assert torch.equal(o, solo)
+        assert elem_err(to_host(o), ref) <= F32_ELEM
+    t = rhos[0].clone()
+    plans[0].solve(t, out=t)
+    torch.cuda.synchronize()
+    assert elem_err(to_host(t), refs[0]) <= F32_ELEM
 
 
 @pytest.mark.parametrize("chunks,gather", [("3", "0"), ("1", "0"), ("3", "2048")])
