@@ -805,12 +805,12 @@ static fsp::SolveGeom group_geom(const fsp_plan_s* p, const int* var) {
   const fsp::PlaneCfg pcf = f64 ? fsp::plane_cfg<double>(p->n[2]) : fsp::plane_cfg<float>(p->n[2]);
   const bool plane_fwd = var[0] == fsp::PLANE, plane_inv = var[3] == fsp::PLANE;
   auto row_pid = [&](int v) { return f64 ? fsp::row_cfg<double>(p->n[2], v).pid : fsp::row_cfg<float>(p->n[2], v).pid; };
-  const int pr1 = plane_fwd ? pcf.pidr : row_pid(var[0]);
-  const int pr5 = plane_inv ? pcf.pidr : row_pid(var[4]);
+  const int pr1 = plane_fwd ? pcf.pid : row_pid(var[0]);
+  const int pr5 = plane_inv ? pcf.pid : row_pid(var[4]);
   const bool fused = var[1] == fsp::FUSED;
   auto col_pid = [&](int L, int v) { return f64 ? fsp::col_cfg<double>(L, v).pid : fsp::col_cfg<float>(L, v).pid; };
-  const int pc2 = fused ? 0 : plane_fwd ? pcf.pidc : col_pid(2 * p->n[1], var[1]);
-  const int pc4 = fused ? 0 : plane_inv ? pcf.pidc : col_pid(2 * p->n[1], var[3]);
+  const int pc2 = fused || plane_fwd ? 0 : col_pid(2 * p->n[1], var[1]);
+  const int pc4 = fused || plane_inv ? 0 : col_pid(2 * p->n[1], var[3]);
   const int pc3 = fused ? 0
                   : f64 ? fsp::conv_cfg<double>(2 * p->n[0], var[2]).pid
                         : fsp::conv_cfg<float>(2 * p->n[0], var[2]).pid;

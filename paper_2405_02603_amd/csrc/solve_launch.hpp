@@ -436,7 +436,6 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
         pa.out[i] = g.work[i];
       }
       pa.twr = g.tw_row[0];
-      pa.twc = g.tw_c1[1];
       return launch_plane<T>(g.n2, g.n0, false, pa, g.items, s);
     }
     if (pass == 3 && plane_inv) {
@@ -445,7 +444,6 @@ hipError_t launch_solve(const SolveGeom& g, int first, int last, hipStream_t s) 
         pa.out[i] = result[i];
       }
       pa.twr = g.tw_row[4];
-      pa.twc = g.tw_c1[3];
       return launch_plane<T>(g.n2, g.n0, true, pa, npost, s);
     }
     switch (pass) {
