@@ -360,7 +360,7 @@ def run_batch(args, count=None, steps=None, warmup=None):
     import torch
 
     import workloads as W
-    from paper_2405_02603_amd import Batch, Plan
+    from paper_2405_02603_amd import Batch, Plan, autotune_batch
 
     count = count or args.batch_count
     steps = steps or args.steps
@@ -384,6 +384,8 @@ def run_batch(args, count=None, steps=None, warmup=None):
         host.append(r)
         plans.append(p)
         rhos.append(torch.from_numpy(r).to("cuda", torch.float32))
+    if not args.no_autotune:   # schedules of the equal-shape groups with their solves timed together
+        autotune_batch(plans, rhos, reps=4)
     batch = Batch(plans, rhos)
     for _ in range(warmup):
         batch.launch()
@@ -393,7 +395,8 @@ def run_batch(args, count=None, steps=None, warmup=None):
         batch.launch()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    model = sum(p.model_bytes for p in plans)
+    model = sum(p.model_bytes for p in plans)   # the bytes of each plan's schedule
+    five_pass = sum(sum(pass_bytes(W._as3(it.n, int), 4)) for it in items)
     # the same right-hand sides as plain float64 single solves, one at a time
     p64 = {}
     r64 = [torch.from_numpy(h).to("cuda") for h in host]
@@ -415,9 +418,12 @@ def run_batch(args, count=None, steps=None, warmup=None):
     out = {"solves_per_s": round(len(items) * 1e3 / ms, 1), "ms_per_step": round(ms, 4), "count": len(items),
            "sizes": sizes, "steps": steps, "hbm_frac_model": round(model / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
            "model_bytes_per_step": model,
+           "five_pass_model_bytes_per_step": five_pass,
+           "hbm_frac_five_pass_model": round(five_pass / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
            "fp64_single_solves": {"solves_per_s": round(len(items) * 1e3 / ms64, 1), "ms_per_batch": round(ms64, 4)},
            "max_rel_l2_f32_vs_gpu_f64": err,
-           "schedules": {str(k): v for k, v in sorted(tuned.items())}}
+           "schedules": {str(k): v for k, v in sorted(tuned.items())},
+           "batch_schedules": {str(it.n): p.schedule for it, p in sorted(zip(items, plans), key=lambda x: x[0].n)}}
     batch.close()
     return out
 

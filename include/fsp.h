@@ -255,6 +255,24 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
 fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const* rho,
                              void* const* phi, void* stream);
 
+/* Schedules for a set of solves launched together (no passage of the paper:
+ * how the passes map onto the GPU).  Plans are grouped by grid, precision
+ * and layout, whatever their schedules.  For each group on a grid that
+ * supports the plane kernels, the group's solves are timed together (reps
+ * timed launches of the whole group after a warm one, 1 <= reps <= 8, median)
+ * with the separate passes fsp_autotune last found fastest for that grid
+ * (else the first plan's), with the plane kernel for passes 0-1, for passes
+ * 3-4, and for both, the axis-0 variant as last tuned; the fastest is set on
+ * every plan of the group.  Groups whose tuned schedule is the fused slab
+ * keep their schedules.  A single solve may prefer another
+ * schedule than many solves launched together: a plane kernel has one block
+ * per plane, too few to fill the GPU for one small grid.  Other groups keep
+ * their schedules.  rho[i] and phi[i] as in fsp_solve_batched, phi[i] must not
+ * overlap rho[i] (FSP_ERR_INVALID_ARG): the timed solves write phi.  Plans not
+ * ready: FSP_ERR_NOT_READY.  Synchronises `stream`; allocates nothing. */
+fsp_status fsp_autotune_batch(int count, const fsp_plan* plans, const void* const* rho, void* const* phi, int reps,
+                              void* stream);
+
 /* A set of solves replayed as one HIP graph (no per-call launch cost; no
  * passage of the paper: a launch-cost device of this library).
  * fsp_batch_create records count (plan, rho, phi) triples with the rules of

@@ -18,7 +18,7 @@ from typing import Iterable, List, Optional, Sequence
 from . import _lib
 from ._lib import FspError, GREENS, PREC, check
 
-__all__ = ["Plan", "Batch", "solve_batched", "FspError", "GREENS", "PREC", "library_path", "version"]
+__all__ = ["Plan", "Batch", "solve_batched", "autotune_batch", "FspError", "GREENS", "PREC", "library_path", "version"]
 
 _DTYPES = {"f32": "float32", "f64": "float64"}
 
@@ -253,7 +253,9 @@ class Plan:
         check(self._lib.fsp_plan_set_schedule(self._h, arr), "fsp_plan_set_schedule")
 
     def autotune(self, rho, out=None, reps: int = 4, stream=None):
-        """Time every pass variant on rho (see fsp_autotune); returns {pass: [ms per variant]}."""
+        """Time every pass variant on rho (see fsp_autotune); returns {pass: [ms per variant]} and the
+        whole-solve times of the schedules built from them (solve_separate, solve_fused, solve_plane,
+        solve_plane_fwd, solve_plane_inv)."""
         torch = _torch()
         self._check_field(rho, "rho")
         if out is None:
@@ -314,6 +316,32 @@ def solve_batched(plans: Sequence[Plan], rhos: Sequence, outs: Optional[Sequence
     with torch.cuda.device(plans[0].device):
         check(lib.fsp_solve_batched(count, hp, rp, op, _stream_ptr(stream)), "fsp_solve_batched")
     return list(outs)
+
+
+def autotune_batch(plans: Sequence[Plan], rhos: Sequence, outs: Optional[Sequence] = None, reps: int = 4,
+                   stream=None) -> None:
+    """Choose each equal-shape group's schedule with the group's solves timed together
+    (fsp_autotune_batch); the plans keep the chosen schedules."""
+    torch = _torch()
+    count = len(plans)
+    if len(rhos) != count:
+        raise ValueError("need one rho per plan")
+    if outs is None:
+        outs = [torch.empty_like(r) for r in rhos]
+    if len(outs) != count:
+        raise ValueError("need one output per plan")
+    for p, r, o in zip(plans, rhos, outs):
+        p._check_field(r, "rho")
+        p._check_field(o, "out")
+    if count == 0:
+        return
+    arr = ctypes.c_void_p * count
+    hp = arr(*[p.handle.value for p in plans])
+    rp = arr(*[r.data_ptr() for r in rhos])
+    op = arr(*[o.data_ptr() for o in outs])
+    lib = _lib.load()
+    with torch.cuda.device(plans[0].device):
+        check(lib.fsp_autotune_batch(count, hp, rp, op, int(reps), _stream_ptr(stream)), "fsp_autotune_batch")
 
 
 class Batch:

@@ -34,7 +34,7 @@ EXPORTS = (
     "fsp_plan_share_ghat", "fsp_precompute", "fsp_solve", "fsp_solve_passes", "fsp_solve_batched", "fsp_plan_destroy",
     "fsp_plan_ghat_layout", "fsp_plan_model_bytes", "fsp_status_str", "fsp_last_error", "fsp_version",
     "fsp_batch_create", "fsp_batch_launch", "fsp_batch_destroy", "fsp_batch_set_io",
-    "fsp_plan_get_schedule", "fsp_plan_set_schedule", "fsp_autotune",
+    "fsp_plan_get_schedule", "fsp_plan_set_schedule", "fsp_autotune", "fsp_autotune_batch",
     "fsp_solve_grad", "fsp_plan_octant_offset", "fsp_solve_static",
 )
 
@@ -143,6 +143,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
         "fsp_plan_get_schedule": (c_int, [P, POINTER(c_int)]),
         "fsp_plan_set_schedule": (c_int, [P, POINTER(c_int)]),
         "fsp_autotune": (c_int, [P, P, P, c_int, P, POINTER(ctypes.c_float)]),
+        "fsp_autotune_batch": (c_int, [c_int, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), c_int, P]),
         "fsp_batch_destroy": (c_int, [P]),
         "fsp_plan_ghat_layout": (c_int, [P, POINTER(c_size_t), POINTER(c_int)]),
         "fsp_plan_model_bytes": (c_int, [P, POINTER(c_double)]),

@@ -274,6 +274,7 @@ struct fsp_plan_s {
   int grad_p3 = -1;         // axis-0 variant of the gradient solve (-1: from the schedule)
   size_t work1_bytes = 0;   // one workspace S (the gradient's other spectra follow it)
   int var[5]{};  // schedule variant of each pass
+  int sep[5]{};  // the fastest separate-pass variants found by fsp_autotune (whatever schedule it kept)
   size_t ghat_bytes = 0, work_bytes = 0, pre_bytes = 0;
   std::vector<char> tw_host;      // image of [0, oct_off) of the Green's buffer
   std::vector<double> cmat_host;  // cosine matrices used by the precompute
@@ -324,7 +325,7 @@ struct TuneKey {
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::array<int, 6>> g_tuned;  // schedule, then the gradient's axis-0 variant
+std::map<TuneKey, std::array<int, 11>> g_tuned;  // schedule, the gradient's axis-0 variant, separate variants
 
 double model_bytes(const fsp_plan_s* p) {
   // P1 reads rho, writes (n2+1) n1 n0 complex; P2 reads that, writes 2 n1 (n2+1) n0;
@@ -449,6 +450,7 @@ fsp_status fsp_plan_create(const fsp_plan_desc* desc, fsp_plan* out) {
     if (it != g_tuned.end()) {
       for (int i = 0; i < 5; ++i) p->var[i] = it->second[i];
       p->grad_p3 = it->second[5];
+      for (int i = 0; i < 5; ++i) p->sep[i] = it->second[6 + i];
     }
   }
   // the column kernels address a pencil's rows with 32-bit element offsets
@@ -831,6 +833,12 @@ static void add_item(fsp::SolveGeom& g, const fsp_plan_s* p, const void* rho, vo
   g.phi[i] = phi;
 }
 
+// Same grid, precision and layout (schedules may differ).
+static bool same_geometry(const fsp_plan_s* a, const fsp_plan_s* b) {
+  return a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] && a->d.prec == b->d.prec &&
+         a->pitch == b->pitch && a->plane == b->plane && a->chunks == b->chunks && a->gather_min == b->gather_min;
+}
+
 static bool same_shape(const fsp_plan_s* a, const fsp_plan_s* b) {
   bool same = a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] && a->d.prec == b->d.prec &&
               a->pitch == b->pitch && a->plane == b->plane && a->chunks == b->chunks &&
@@ -1149,6 +1157,7 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
       }
     }
   }
+  for (int i = 0; i < 5; ++i) p->sep[i] = best[i];
   // whole-solve schedules built from the best separate variants: the separate
   // passes, the fused slab (passes 1-3), the plane kernels for passes 0-1 and
   // 3-4 (both pairs, or either alone); each timed as a full solve, the fastest kept
@@ -1230,10 +1239,11 @@ fsp_status fsp_autotune(fsp_plan p, const void* rho, void* phi, int reps, void* 
   if (st != FSP_OK) return st;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    std::array<int, 6> a;
+    std::array<int, 11> a;
     for (int i = 0; i < 5; ++i) a[i] = best[i];
     auto it = g_tuned.find(TuneKey{p->n[0], p->n[1], p->n[2], p->d.prec});
     a[5] = p->grad ? p->grad_p3 : it != g_tuned.end() ? it->second[5] : -1;
+    for (int i = 0; i < 5; ++i) a[6 + i] = p->sep[i];
     g_tuned[TuneKey{p->n[0], p->n[1], p->n[2], p->d.prec}] = a;
   }
   return FSP_OK;
@@ -1248,6 +1258,87 @@ fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const
   if (e != hipSuccess) return fail_hip(e, "fsp_solve_batched: hipSetDevice");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return enqueue_batch(count, plans, rho, phi, &s, 1);
+}
+
+fsp_status fsp_autotune_batch(int count, const fsp_plan* plans, const void* const* rho, void* const* phi, int reps,
+                              void* stream) {
+  fsp_status st = check_batch("fsp_autotune_batch", count, plans, rho, phi);
+  if (st != FSP_OK || count == 0) return st;
+  if (reps < 1 || reps > 8) return fail(FSP_ERR_INVALID_ARG, "fsp_autotune_batch: reps must be in [1, 8]");
+  for (int i = 0; i < count; ++i) {
+    const size_t field = (size_t)plans[i]->n[0] * plans[i]->n[1] * plans[i]->n[2] * plans[i]->rb;
+    const char *r = static_cast<const char*>(rho[i]), *f = static_cast<const char*>(phi[i]);
+    if (r < f + field && f < r + field) return fail(FSP_ERR_INVALID_ARG, "fsp_autotune_batch: a phi overlaps its rho");
+  }
+  DeviceGuard guard;
+  hipError_t e = guard.enter(plans[0]->device);
+  if (e != hipSuccess) return fail_hip(e, "fsp_autotune_batch: hipSetDevice");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  std::vector<char> done(count, 0);
+  for (int i = 0; i < count && e == hipSuccess; ++i) {
+    if (done[i]) continue;
+    std::vector<fsp_plan> gp;
+    std::vector<const void*> gr;
+    std::vector<void*> gf;
+    for (int j = i; j < count; ++j) {
+      if (done[j] || !same_geometry(plans[i], plans[j])) continue;
+      done[j] = 1;
+      gp.push_back(plans[j]);
+      gr.push_back(rho[j]);
+      gf.push_back(phi[j]);
+    }
+    const fsp_plan p0 = gp[0];
+    // the schedule and separate variants last tuned for this shape, else the first plan's
+    int base[5], sp[5];
+    for (int k = 0; k < 5; ++k) base[k] = p0->var[k], sp[k] = p0->sep[k];
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tuned.find(TuneKey{p0->n[0], p0->n[1], p0->n[2], p0->d.prec});
+      if (it != g_tuned.end())
+        for (int k = 0; k < 5; ++k) base[k] = it->second[k], sp[k] = it->second[6 + k];
+    }
+    if (base[1] == fsp::FUSED || !plane_supported(p0)) continue;  // nothing to choose between
+    std::vector<std::array<int, 5>> orig;
+    for (fsp_plan q : gp) orig.push_back({q->var[0], q->var[1], q->var[2], q->var[3], q->var[4]});
+    const int P = fsp::PLANE;
+    const int cand[4][5] = {{sp[0], sp[1], base[2], sp[3], sp[4]},
+                            {P, P, base[2], sp[3], sp[4]},
+                            {sp[0], sp[1], base[2], P, P},
+                            {P, P, base[2], P, P}};
+    float best_ms = 1e30f;
+    int pick = -1;
+    for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+      for (fsp_plan q : gp)
+        for (int k = 0; k < 5; ++k) q->var[k] = cand[c][k];
+      float rep_ms[8] = {};
+      for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // r == 0 warms up
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) {
+          st = enqueue_batch((int)gp.size(), gp.data(), gr.data(), gf.data(), &s, 1);
+          if (st != FSP_OK) break;
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (r > 0) rep_ms[r - 1] = ms;
+      }
+      if (st != FSP_OK) break;
+      const float ms = median_ms(rep_ms, reps);
+      if (e == hipSuccess && ms < best_ms) best_ms = ms, pick = c;
+    }
+    for (size_t m = 0; m < gp.size(); ++m)
+      for (int k = 0; k < 5; ++k) gp[m]->var[k] = pick >= 0 ? cand[pick][k] : orig[m][k];
+    if (st != FSP_OK) break;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st != FSP_OK) return st;
+  if (e != hipSuccess) return fail_hip(e, "fsp_autotune_batch");
+  return FSP_OK;
 }
 
 fsp_status fsp_plan_destroy(fsp_plan p) {

@@ -48,28 +48,32 @@ struct PlaneArgs {
 
 // Shape of the plane kernels for n1 == n2 == N: radix plan of length N (rows
 // and columns), threads per row, column tile and threads per column pencil
-// (TC * NQC threads a block, NT / NQR rows per row group).  tc == 0: not built.
+// (TC * NQC threads a block, NT / NQR rows per row group), and the waves per
+// SIMD the kernels are built for (the resident blocks' waves: registers are
+// held to that).  tc == 0: not built.  Blocks with 64 KB or more of LDS use
+// 4 or 8 waves: two such blocks of 6 waves did not share a compute unit on
+// MI355X, two of 8 did.
 struct PlaneCfg {
-  int pid, nqr, tc, nqc;
+  int pid, nqr, tc, nqc, wpe;
 };
 
 template <typename T>
 __host__ __device__ constexpr PlaneCfg plane_cfg(int N) {
   if constexpr (sizeof(T) == 4) {
     switch (N) {
-      case 32: return {0, 4, 32, 4};
-      case 48: return {1, 4, 16, 12};
-      case 64: return {0, 4, 32, 8};
-      case 96: return {0, 4, 32, 12};
-      case 128: return {1, 4, 32, 16};
-      default: return {0, 0, 0, 0};
+      case 32: return {0, 4, 32, 4, 2};
+      case 48: return {1, 4, 16, 12, 4};
+      case 64: return {0, 4, 32, 8, 4};
+      case 96: return {0, 16, 32, 16, 4};
+      case 128: return {1, 4, 32, 16, 2};
+      default: return {0, 0, 0, 0, 0};
     }
   } else {
     switch (N) {
-      case 32: return {0, 4, 32, 4};
-      case 48: return {1, 4, 16, 12};
-      case 64: return {0, 4, 16, 8};
-      default: return {0, 0, 0, 0};
+      case 32: return {0, 4, 32, 4, 2};
+      case 48: return {1, 4, 16, 12, 2};
+      case 64: return {0, 4, 16, 8, 1};
+      default: return {0, 0, 0, 0, 0};
     }
   }
 }
@@ -94,8 +98,8 @@ __device__ __forceinline__ void plane_column_fft(cx<T>* pl, const cx<T>* tw, int
   lds_last_stage<T, N, PID, INV, NQC, INV>(pl, tw, q, idx, w);
 }
 
-template <typename T, int N, int PID, int NQR, int TC, int NQC>
-__global__ __launch_bounds__(TC* NQC) void k_plane_fwd(PlaneArgs a) {
+template <typename T, int N, int PID, int NQR, int TC, int NQC, int WPE>
+__global__ __launch_bounds__(TC* NQC, WPE) void k_plane_fwd(PlaneArgs a) {
   constexpr int LC = N, NT = TC * NQC, TRR = NT / NQR, G = N / TRR;
   static_assert(NT % NQR == 0 && N % TRR == 0 && N % TC == 0, "row groups and column tiles tile the plane");
   constexpr int PP = row_pitch(LC);
@@ -229,8 +233,8 @@ __global__ __launch_bounds__(TC* NQC) void k_plane_fwd(PlaneArgs a) {
   }
 }
 
-template <typename T, int N, int PID, int NQR, int TC, int NQC>
-__global__ __launch_bounds__(TC* NQC) void k_plane_inv(PlaneArgs a) {
+template <typename T, int N, int PID, int NQR, int TC, int NQC, int WPE>
+__global__ __launch_bounds__(TC* NQC, WPE) void k_plane_inv(PlaneArgs a) {
   constexpr int LC = N, NT = TC * NQC, TRR = NT / NQR, G = N / TRR;
   static_assert(NT % NQR == 0 && N % TRR == 0 && N % TC == 0, "row groups and column tiles tile the plane");
   constexpr int PP = row_pitch(LC);
@@ -369,10 +373,10 @@ hipError_t launch_plane(int N, int n0, bool inv, const PlaneArgs& a, int items, 
     if constexpr (c.tc > 0) {                                                                       \
       static_assert(plane_lds_bytes<T>(NV) <= 163840, "the plane fits in LDS"); \
       if (inv)                                                                                      \
-        hipLaunchKernelGGL((k_plane_inv<T, NV, c.pid, c.nqr, c.tc, c.nqc>), dim3(n0, items),         \
+        hipLaunchKernelGGL((k_plane_inv<T, NV, c.pid, c.nqr, c.tc, c.nqc, c.wpe>), dim3(n0, items),         \
                            dim3(c.tc * c.nqc), 0, s, a);                                            \
       else                                                                                          \
-        hipLaunchKernelGGL((k_plane_fwd<T, NV, c.pid, c.nqr, c.tc, c.nqc>), dim3(n0, items),         \
+        hipLaunchKernelGGL((k_plane_fwd<T, NV, c.pid, c.nqr, c.tc, c.nqc, c.wpe>), dim3(n0, items),         \
                            dim3(c.tc * c.nqc), 0, s, a);                                            \
       found = true;                                                                                 \
     }                                                                                               \

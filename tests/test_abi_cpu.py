@@ -294,6 +294,18 @@ def test_static_scratch_size_matches_header():
     assert m and int(m.group(1)) * 1024 * 1024 == _lib.STATIC_SCRATCH_BYTES
 
 
+def test_autotune_batch_arguments(lib):
+    arr = ctypes.c_void_p * 1
+    assert lib.fsp_autotune_batch(0, None, None, None, 2, None) == _lib.FSP_OK
+    assert lib.fsp_autotune_batch(-1, None, None, None, 2, None) == _lib.FSP_ERR_INVALID_ARG
+    assert lib.fsp_autotune_batch(1, None, None, None, 2, None) == _lib.FSP_ERR_INVALID_ARG
+    st, h = _create(lib, _desc(n=32))
+    d = ctypes.c_void_p(256)
+    # an unbound plan is not ready (the check precedes any device work)
+    assert lib.fsp_autotune_batch(1, arr(h.value), arr(d.value), arr(d.value), 2, None) == _lib.FSP_ERR_NOT_READY
+    lib.fsp_plan_destroy(h)
+
+
 def test_autotune_rejects_aliased_rho_phi(lib):
     """The tuning solves write phi many times, so phi may not overlap rho; checked on
     the host before the plan's state."""

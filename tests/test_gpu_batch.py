@@ -149,3 +149,37 @@ def test_batch_new_inputs_without_capture_and_large_group(torch_cuda):
     for p, r, o in zip(plans, rhos, outs1):
         assert torch.equal(p.solve(r), o)
     batch.close()
+
+
+def test_autotune_batch_then_graph(torch_cuda):
+    """Schedules chosen with each shape's solves timed together (fsp_autotune_batch): every group
+    keeps one schedule, a captured batch with them equals the solo solves bit for bit and every item
+    equals the oracle."""
+    torch = torch_cuda
+    from paper_2405_02603_amd import Batch, _lib, autotune_batch
+    items = _mix(20, seed=9, sizes=(32, 48, 64, 96))
+    plans, rhos, host = _plans_and_inputs(torch, items)
+    tuned = set()
+    for p, r, it in zip(plans, rhos, items):
+        if it.n not in tuned:
+            p.autotune(r, reps=1)
+            tuned.add(it.n)
+    autotune_batch(plans, rhos, reps=2)
+    torch.cuda.synchronize()
+    by_size = {}
+    for p, it in zip(plans, items):
+        by_size.setdefault(it.n, set()).add(tuple(p.schedule))
+    for n, scheds in by_size.items():
+        assert len(scheds) == 1, (n, scheds)
+        s = next(iter(scheds))
+        assert (s[0] == _lib.PLANE) == (s[1] == _lib.PLANE) and (s[3] == _lib.PLANE) == (s[4] == _lib.PLANE), s
+    batch = Batch(plans, rhos)
+    batch.launch()
+    torch.cuda.synchronize()
+    for i, (p, r, it) in enumerate(zip(plans, rhos, items)):
+        solo = p.solve(r)
+        torch.cuda.synchronize()
+        assert torch.equal(solo, batch.outs[i]), (i, it.n, p.schedule)
+        ref = reference(host[i], "vico_dct", it.lo, it.hi, use_direct=False)
+        assert elem_err(to_host(batch.outs[i]), ref) <= F32_ELEM, (i, it.n)
+    batch.close()
