@@ -664,8 +664,9 @@ __device__ __forceinline__ void exchange_split(T* lds, const cx<T> (&v)[J][R], c
   }
 }
 
-// The last stage on inputs already in registers (after exchange_split).
-template <typename T, int L, int PID, bool REV, int NQ, bool INV, bool HALF, int J, int R>
+// The last stage on inputs already in registers (after exchange_split);
+// FULL: tw is the complete table (as in lds_last_stage).
+template <typename T, int L, int PID, bool REV, int NQ, bool INV, bool HALF, bool FULL = false, int J, int R>
 __device__ __forceinline__ void last_stage_regs(cx<T> (&v)[J][R], const cx<T>* __restrict__ tw, int q) {
   constexpr int S = plan_len(L, PID) - 1;
   constexpr int NB = L / R;
@@ -675,7 +676,7 @@ __device__ __forceinline__ void last_stage_regs(cx<T> (&v)[J][R], const cx<T>* _
   for (int j = 0; j < J; ++j) {
     const int b = q + NQ * j;
     if ((NB % NQ == 0) || b < NB) {
-      stage_twiddles<T, L, PID, REV, S, INV, false>(v[j], tw, b);
+      stage_twiddles<T, L, PID, REV, S, INV, FULL>(v[j], tw, b);
       if constexpr (HALF)
         dft_half_out<R, INV, T>(v[j]);
       else

@@ -228,7 +228,7 @@ __global__ __launch_bounds__(TC* NQ, WPE) void k_col_conv(ColArgs a) {
   constexpr bool GRAD = NOUT > 0;
   constexpr int K = plan_len(L, PID);
   static_assert(!TWF || K > 1, "single-stage plans have no twiddles");
-  static_assert(!SPLIT || (K == 2 && !TWF), "split exchanges are built for two-stage plans without the table");
+  static_assert(!SPLIT || K == 2, "split exchanges are built for two-stage plans");
   // the others keep their registers for occupancy (at 1024 points the preloaded values spill)
   constexpr bool PRE = K == 2 && !TWF && !GRAD && !SPLIT && sizeof(T) == 4 && L <= 512;
   constexpr int NT = TC * NQ;
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(TC* NQ, WPE) void k_col_conv(ColArgs a) {
       lds_barrier();
       if constexpr (SPLIT) {
         exchange_split<T, Lf::R, Lf::J, Lf::NB, NQ, Li::R, Li::J, Li::NB>(ldss, x, u, q, idxs);
-        last_stage_regs<T, L, PID, true, NQ, true, true>(u, tws, q);
+        last_stage_regs<T, L, PID, true, NQ, true, true, TWF>(u, tws, q);
       } else {
         write_first_outputs<T, Lf::R, Lf::J, Lf::NB, NQ>(lds, x, q, idx);
         lds_barrier();
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(TC* NQ, WPE) void k_col_conv(ColArgs a) {
         for (int m = 0; m < Lf::R; ++m) w[j][m] = v[j][m];
     } else if constexpr (SPLIT) {
       exchange_split<T, F::R, F::J, F::NB, NQ, Lf::R, Lf::J, Lf::NB>(ldss, v, w, q, idxs);
-      last_stage_regs<T, L, PID, false, NQ, false, false>(w, tws, q);
+      last_stage_regs<T, L, PID, false, NQ, false, false, TWF>(w, tws, q);
     } else {
       write_first_outputs<T, F::R, F::J, F::NB, NQ>(lds, v, q, idx);
       lds_barrier();

@@ -89,9 +89,9 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
 // Axis-0 pass variants: variant 0 as col_cfg, variant 1 as col_cfg or the
 // split-exchange form (conv_split_wpe, below); variant 2 keeps the
 // complete twiddle table in LDS, with the shape of variant 0 (else 1) when the
-// table costs no resident block (conv_twf_fits), else it is the pipelined
-// persistent kernel (grid of at most CONV_PIPE_BLOCKS blocks) with the shape
-// of variant 1.
+// table costs no resident block (conv_twf_fits), and with the split
+// exchanges too where variant 1 has them; else it is the pipelined persistent
+// kernel (grid of at most CONV_PIPE_BLOCKS blocks) with the shape of variant 1.
 constexpr int CONV_PIPE_BLOCKS = 1024;
 constexpr int CONV_GATHER_MIN_BLOCKS = 2048;
 constexpr int CONV_LDS_PER_CU = 163840;
@@ -250,7 +250,11 @@ hipError_t launch_col(int L, int v, int kind, const ColArgs& a, int items, hipSt
       } else {                                                                                      \
         const ColArgs b = conv_gather(a, cc.tiles);                                                 \
         const dim3 gridc((unsigned)(b.nouter * b.ntiles + b.ntail), (unsigned)items);               \
-        if constexpr (conv_twf<T>(LV, VV))                                                          \
+        if constexpr (conv_twf<T>(LV, VV) && conv_split_wpe<T>(LV) > 0)                            \
+          hipLaunchKernelGGL((k_col_conv<T, LV, cc.pid, cc.tiles, cc.nq, true, 0, true,             \
+                                         conv_split_wpe<T>(LV)>),                                   \
+                             gridc, dim3(cc.tiles * cc.nq), 0, s, b);                               \
+        else if constexpr (conv_twf<T>(LV, VV))                                                     \
           hipLaunchKernelGGL((k_col_conv<T, LV, cc.pid, cc.tiles, cc.nq, true>), gridc,             \
                              dim3(cc.tiles * cc.nq), 0, s, b);                                      \
         else if constexpr (VV == 1 && conv_split_wpe<T>(LV) > 0)                                    \
