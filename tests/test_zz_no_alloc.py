@@ -34,11 +34,13 @@ def _static(torch, lib, plan, rho, phi):
     assert st == _lib.FSP_OK, lib.fsp_last_error().decode()
 
 
-def _case(torch, lib, n, lo, hi, kind, prec, seed, in_place=False):
+def _case(torch, lib, n, lo, hi, kind, prec, seed, in_place=False, sched=None):
     from paper_2405_02603_amd import Plan
     dt = torch.float64 if prec == "f64" else torch.float32
-    print(f"no-alloc case n={n} {kind} {prec} seed={seed} in_place={in_place}", flush=True)
+    print(f"no-alloc case n={n} {kind} {prec} seed={seed} in_place={in_place} sched={sched}", flush=True)
     plan = Plan(n=n, lo=lo, hi=hi, greens=kind, prec=prec)
+    if sched is not None:
+        plan.schedule = sched
     host = W.random_field(n, seed)
     rho = to_dev(host, dt)
     ref = plan.solve(rho)                          # fsp_solve: the plan's own workspace
@@ -78,3 +80,13 @@ def test_static_rejects_oversize_plan(torch_cuda):
     st = lib.fsp_solve_static(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()), None)
     assert st == _lib.FSP_ERR_UNSUPPORTED_SIZE
     assert b"scratch" in lib.fsp_last_error()
+
+
+def test_static_with_fused_schedules(torch_cuda):
+    """The static workspace serves the plane kernels and the fused slab as well (one spectrum)."""
+    from paper_2405_02603_amd import _lib
+    lib = _lib.load()
+    P, F = _lib.PLANE, _lib.FUSED
+    _case(torch_cuda, lib, (24, 64, 64), (-1.0,) * 3, (1.0,) * 3, "vico_dct", "f32", 15, sched=[P, P, 0, P, P])
+    _case(torch_cuda, lib, (32, 32, 32), (-0.5,) * 3, (0.5,) * 3, "hockney", "f64", 16, sched=[P, P, 1, 0, 0])
+    _case(torch_cuda, lib, (32, 32, 16), (-0.5,) * 3, (0.5,) * 3, "vico_dct", "f32", 17, sched=[0, F, F, F, 0])
