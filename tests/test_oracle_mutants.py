@@ -138,3 +138,129 @@ def test_planted_mistake_fails_a_pin(name, golden_dir, monkeypatch):
     failed = _failing(golden_dir)
     print(f"{name}: caught by {failed}")
     assert failed, f"no pin catches: {name}"
+
+
+# ------------------------------------------------- the gradient and mixed-axis oracles
+import itertools  # noqa: E402
+
+import test_oracle_grad as TG  # noqa: E402
+import test_oracle_mixed as TM  # noqa: E402
+from oracle import gradient, mixed  # noqa: E402
+
+MASKS = list(itertools.product([False, True], repeat=3))
+
+
+def _grad_pins():
+    return {
+        "closed-form gradient = FD of potential": TG.test_closed_form_gradient_is_the_derivative_of_the_closed_form_potential,
+        "gradient near the centre": TG.test_closed_form_gradient_near_the_centre,
+        "odd sum == loops": TG.test_direct_odd_sum_equals_loops,
+        "odd sum at points": TG.test_odd_sum_at_points_equals_the_whole_grid_sum,
+        "odd FFT route == odd sum": lambda: [TG.test_fft_route_equals_direct_odd_sum(k) for k in ("hockney", "vico")],
+        "VG derivative two routes": TG.test_vico_derivative_table_two_routes,
+        "HE derivative table": TG.test_hockney_derivative_table_is_odd_and_matches_the_kernel_derivative,
+        "odd transform == FFT": TG.test_odd_transform_equals_fft_of_the_odd_extension,
+        "gradient convergence": TG.test_gradient_convergence_to_the_closed_form,
+    }
+
+
+def _mixed_pins():
+    return {
+        "all open == aperiodic": TM.test_all_open_is_the_aperiodic_sum,
+        "mixed == loops": lambda: [TM.test_sum_equals_six_loops(m) for m in MASKS],
+        "mixed FFT route": lambda: [TM.test_fft_route_with_only_open_axes_doubled(k, m)
+                                    for k in ("hockney", "vico_dct") for m in MASKS],
+        "cyclic shift": lambda: [TM.test_cyclic_shift_along_a_periodic_axis(a) for a in range(3)],
+        "confined source": TM.test_confined_source_sees_no_image,
+        "folded table": lambda: [TM.test_folded_table_gives_the_mixed_sum(m) for m in MASKS],
+    }
+
+
+def _failing_of(pins):
+    failed = []
+    for name, pin in pins.items():
+        try:
+            pin()
+        except Exception:
+            failed.append(name)
+    return failed
+
+
+_orig_hgrad = gradient.hockney_grad_octant
+_orig_sine = gradient._sine_k_matrix
+_orig_signed = gradient.signed_extend
+_orig_dist = mixed.axis_distance
+_orig_table = mixed.periodic_table
+
+
+def _hgrad_sign(n, lo, hi, axis):
+    return -_orig_hgrad(n, lo, hi, axis)
+
+
+def _hgrad_wrong_axis(n, lo, hi, axis):
+    return _orig_hgrad(n, lo, hi, (axis + 1) % 3)
+
+
+def _sine_without_2(n_out, period, kfac):
+    return 0.5 * _orig_sine(n_out, period, kfac)
+
+
+def _signed_flipped(d_oct, n, axis):
+    return -_orig_signed(d_oct, n, axis)
+
+
+def _dist_off_by_one(n, periodic):
+    d = np.abs(np.arange(n)[:, None] - np.arange(n)[None, :])
+    return np.minimum(d, np.maximum(n - d - 1, 0)) if periodic else d
+
+
+def _dist_ignores_periodic(n, periodic):
+    return _orig_dist(n, False)
+
+
+def _solve_mixed_all_doubled(rho, k_oct, h, periodic):
+    return fftroute.solve(rho, k_oct, h)  # every axis doubled: the periodic ones treated as open
+
+
+def _table_off_by_one(k_oct, n, periodic):
+    f = [np.minimum(np.arange(n[a] + 1), np.maximum(n[a] - np.arange(n[a] + 1) - 1, 0)) if periodic[a]
+         else np.arange(n[a] + 1) for a in range(3)]
+    return k_oct[f[0][:, None, None], f[1][None, :, None], f[2][None, None, :]]
+
+
+GRAD_MUTANTS = {
+    "HE derivative table sign flipped": (gradient, "hockney_grad_octant", _hgrad_sign),
+    "HE derivative along the wrong axis": (gradient, "hockney_grad_octant", _hgrad_wrong_axis),
+    "sine sums without their factor 2": (gradient, "_sine_k_matrix", _sine_without_2),
+    "odd extension with the opposite sign": (gradient, "signed_extend", _signed_flipped),
+}
+
+MIXED_MUTANTS = {
+    "nearest image off by one": (mixed, "axis_distance", _dist_off_by_one),
+    "periodic axes summed as open": (mixed, "axis_distance", _dist_ignores_periodic),
+    "FFT route doubling every axis": (mixed, "solve_mixed_fft", _solve_mixed_all_doubled),
+    "folded table off by one": (mixed, "periodic_table", _table_off_by_one),
+}
+
+
+def test_unmodified_gradient_and_mixed_oracles_pass():
+    assert _failing_of(_grad_pins()) == []
+    assert _failing_of(_mixed_pins()) == []
+
+
+@pytest.mark.parametrize("name", list(GRAD_MUTANTS))
+def test_planted_gradient_mistake_fails_a_pin(name, monkeypatch):
+    module, attr, fn = GRAD_MUTANTS[name]
+    monkeypatch.setattr(module, attr, fn)
+    failed = _failing_of(_grad_pins())
+    print(f"{name}: caught by {failed}")
+    assert failed, f"no pin catches: {name}"
+
+
+@pytest.mark.parametrize("name", list(MIXED_MUTANTS))
+def test_planted_mixed_mistake_fails_a_pin(name, monkeypatch):
+    module, attr, fn = MIXED_MUTANTS[name]
+    monkeypatch.setattr(module, attr, fn)
+    failed = _failing_of(_mixed_pins())
+    print(f"{name}: caught by {failed}")
+    assert failed, f"no pin catches: {name}"
