@@ -35,7 +35,9 @@ struct RadixPlan {
 
 // Radix sequences for each supported pencil length (2^a or 3 * 2^a, 8..1024).
 // Plan 0 is the default; plan 1 is an alternative (fewer, larger stages or
-// more, smaller ones) the autotuner may pick.  The first radix is always even.
+// more, smaller ones) the autotuner may pick: at 96, 192 and 384 it is the
+// two-stage plan ending in radix 12 or 24, one LDS exchange fewer than plan 0.
+// The first radix is always even and divides 32.
 constexpr int NUM_PLANS = 2;
 
 __host__ __device__ constexpr RadixPlan radix_plan(int L, int pid = 0) {
@@ -48,11 +50,11 @@ __host__ __device__ constexpr RadixPlan radix_plan(int L, int pid = 0) {
       case 32: return {2, {16, 2, 0, 0}};
       case 48: return {3, {4, 4, 3, 0}};
       case 64: return {2, {16, 4, 0, 0}};
-      case 96: return {3, {16, 2, 3, 0}};
+      case 96: return {2, {8, 12, 0, 0}};
       case 128: return {2, {8, 16, 0, 0}};
-      case 192: return {3, {16, 4, 3, 0}};
+      case 192: return {2, {8, 24, 0, 0}};
       case 256: return {3, {8, 4, 8, 0}};
-      case 384: return {3, {8, 16, 3, 0}};
+      case 384: return {2, {16, 24, 0, 0}};
       case 512: return {3, {8, 8, 8, 0}};
       case 768: return {4, {16, 4, 4, 3}};
       case 1024: return {3, {16, 8, 8, 0}};
@@ -312,6 +314,50 @@ struct Dft<32, INV, T> {
   }
 };
 
+// Multiplicative inverse of a modulo m (a, m coprime; 1 when m == 1).
+__host__ __device__ constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
+// Length N1 N2 DFT for coprime N1, N2 by the prime-factor (Good-Thomas) index
+// maps, which need no twiddles between the two layers: input n = (N2 n1 + N1 n2)
+// mod N feeds length-N1 DFTs over n1, then length-N2 DFTs over n2 give output
+// k = (N2 u k1 + N1 t k2) mod N, u = N2^-1 mod N1, t = N1^-1 mod N2.
+template <int N1, int N2, bool INV, typename T>
+__device__ __forceinline__ void dft_pfa(cx<T>* v) {
+  constexpr int N = N1 * N2;
+  constexpr int U = inv_mod(N2 % N1, N1), TT = inv_mod(N1 % N2, N2);
+  cx<T> a[N2][N1];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) a[n2][n1] = v[(N2 * n1 + N1 * n2) % N];
+    Dft<N1, INV, T>::run(a[n2]);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) {
+    cx<T> b[N2];
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) b[n2] = a[n2][k1];
+    Dft<N2, INV, T>::run(b);
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) v[(N2 * U * k1 + N1 * TT * k2) % N] = b[k2];
+  }
+}
+
+// Radices 12 = 3 x 4 and 24 = 8 x 3 (the last stage of the two-stage plans of
+// lengths 3 * 2^a).
+template <bool INV, typename T>
+struct Dft<12, INV, T> {
+  static __device__ __forceinline__ void run(cx<T>* v) { dft_pfa<3, 4, INV, T>(v); }
+};
+template <bool INV, typename T>
+struct Dft<24, INV, T> {
+  static __device__ __forceinline__ void run(cx<T>* v) { dft_pfa<8, 3, INV, T>(v); }
+};
+
 // ---------------------------------------------------------------- pruned butterflies
 // exp(-2 pi i r / R) = (tw_c, tw_s) for r < R / 2, R <= 32 (forward sign; the
 // inverse conjugates through mul_const<INV>).
@@ -343,6 +389,7 @@ __host__ __device__ constexpr double tw_sin(int r, int R) {
 // v[r] *= exp(-+ 2 pi i r / R) for a compile-time r (exact for r = 0 and r = R / 4)
 template <int R, int r, bool INV, typename T>
 __device__ __forceinline__ cx<T> twiddle_const(cx<T> a) {
+  static_assert(32 % R == 0, "constant twiddles of radices dividing 32");
   if constexpr (r == 0) {
     return a;
   } else if constexpr (4 * r == R) {
@@ -468,15 +515,15 @@ __device__ __forceinline__ void apply_twbase(cx<T>* v, const TwBase<T>& t) {
     w[6] = cmul(t.w4, t.w2);
     w[7] = cmul(t.w4, t.w3);
   }
-  if constexpr (R >= 16) {
+  if constexpr (R >= 12) {
     w[8] = t.w8;
 #pragma unroll
-    for (int r = 9; r < 16; ++r) w[r] = cmul(t.w8, w[r - 8]);
+    for (int r = 9; r < (R < 16 ? R : 16); ++r) w[r] = cmul(t.w8, w[r - 8]);
   }
-  if constexpr (R >= 32) {
+  if constexpr (R >= 24) {
     w[16] = t.w16;
 #pragma unroll
-    for (int r = 17; r < 32; ++r) w[r] = cmul(t.w16, w[r - 16]);
+    for (int r = 17; r < R; ++r) w[r] = cmul(t.w16, w[r - 16]);
   }
 #pragma unroll
   for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], w[r]) : cmul(v[r], w[r]);

@@ -46,11 +46,11 @@ __host__ __device__ constexpr TileCfg col_cfg(int L, int v) {
     case 32: return v == 0 ? TileCfg{0, tc, 4} : v == 1 ? TileCfg{1, tc, 2} : TileCfg{0, tc, 8};
     case 48: return v == 0 ? TileCfg{0, tc, 1} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{0, tc, 3};
     case 64: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{0, tc, 4};
-    case 96: return v == 0 ? TileCfg{0, tc, 4} : v == 1 ? TileCfg{1, tc, 2} : TileCfg{0, tc, 8};
+    case 96: return v == 0 ? TileCfg{0, tc, 4} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{0, tc, 8};
     case 128: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 8} : TileCfg{0, tc, 16};
-    case 192: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 4} : TileCfg{0, tc, 16};
+    case 192: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 8} : TileCfg{0, tc, 16};
     case 256: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tw, 16};
-    case 384: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 8} : TileCfg{0, tw, 8};
+    case 384: return v == 0 ? TileCfg{0, tc, 8} : v == 1 ? TileCfg{1, tc, 16} : TileCfg{0, tw, 8};
     case 512: return v == 0 ? TileCfg{0, tc, 16} : v == 1 ? TileCfg{1, tc, 32} : TileCfg{0, tw, 16};
     // one block per compute unit at these lengths (L * TC complex of LDS): variant 2
     // adds threads per pencil instead of columns
@@ -72,9 +72,9 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
     case 32: return v == 0 ? TileCfg{0, 32, 4} : v == 1 ? TileCfg{1, 32, 2} : TileCfg{0, 16, 8};
     case 48: return v == 0 ? TileCfg{0, d ? 32 : 64, 1} : v == 1 ? TileCfg{1, 32, 4} : TileCfg{0, 32, 3};
     case 64: return v == 0 ? TileCfg{0, 32, 8} : v == 1 ? TileCfg{1, 32, 4} : TileCfg{0, 16, 8};
-    case 96: return v == 0 ? TileCfg{0, 32, 4} : v == 1 ? TileCfg{1, 32, 2} : TileCfg{0, 16, 8};
+    case 96: return v == 0 ? TileCfg{0, 32, 4} : v == 1 ? TileCfg{1, 32, 4} : TileCfg{0, 16, 8};
     case 128: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 8} : TileCfg{0, 32, 8};
-    case 192: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 4} : TileCfg{0, 8, 16};
+    case 192: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 8} : TileCfg{0, 8, 16};
     // 256 in float32: small blocks of 4 rows, 2-4 groups each (more bytes in flight a thread)
     case 256:
       return d ? (v == 0 ? TileCfg{0, 8, 16} : v == 1 ? TileCfg{1, 8, 32} : TileCfg{1, 4, 32, 2})
@@ -189,7 +189,9 @@ hipError_t launch_p5(int LC, int v, const RowArgs& a, int items, hipStream_t s) 
 template <typename T>
 __host__ __device__ constexpr TileCfg grad_cfg(int L, int v) {
   const int tc = col_tc<T>(L);
-  if (v == 0 && L >= 256 && L <= 512) return {1, tc, 1024 / tc < L / 8 ? 1024 / tc : L / 8};
+  // (384: plan 0, whose first stages have 24 and 48 butterflies; plan 1's
+  // radix-24 stage has only 16)
+  if (v == 0 && L >= 256 && L <= 512) return {L == 384 ? 0 : 1, tc, 1024 / tc < L / 8 ? 1024 / tc : L / 8};
   if (v == 0 && L > 512) return {1, tc, 512 / tc};
   return col_cfg<T>(L, v == 2 ? 0 : v);
 }

@@ -72,13 +72,15 @@ def test_derivative_octants_f64(torch_cuda, kind, n, lo, hi):
 @pytest.mark.parametrize("kind", ["hockney", "vico_dct"])
 def test_gradient_vs_oracle_every_schedule(torch_cuda, kind, prec, tol):
     """Components and the potential from one call, for every kernel variant; small grids against
-    the direct odd sum, larger ones against the FFT route."""
+    the direct odd sum, larger ones against the FFT route (the axis-0 pencils of 96, 192 and 384
+    points take plans ending in radix 12 and 24 in variant 1)."""
     from paper_2405_02603_amd import _lib
     torch = torch_cuda
     dt = torch.float64 if prec == "f64" else torch.float32
     cases = [(8, (-0.5,) * 3, (0.5,) * 3), ((8, 12, 16), (-1.0, -1.0, -2.0), (1.0, 1.0, 2.0)),
              (24, (0.0,) * 3, (1.0,) * 3), (48, (-1.0,) * 3, (1.0,) * 3), ((32, 64, 48), (-1.0,) * 3, (1.0,) * 3),
-             (64, (-1.0, -1.0, -2.0), (1.0, 1.0, 2.0))]
+             (64, (-1.0, -1.0, -2.0), (1.0, 1.0, 2.0)),
+             ((96, 16, 24), (-1.0,) * 3, (1.0,) * 3), ((192, 8, 12), (-1.0,) * 3, (1.0,) * 3)]
     for n, lo, hi in cases:
         n3 = W._as3(n, int)
         rho = W.random_field(n3, 41)

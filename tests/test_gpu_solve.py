@@ -118,12 +118,14 @@ def test_in_place(torch_cuda):
 @pytest.mark.parametrize("prec,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
 @pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64, 96, 128, (64, 96, 48),
                                (512, 16, 24), (16, 512, 16), (384, 12, 16), (16, 384, 8),
-                               (8, 12, 512), (12, 8, 384), (12, 8, 256), (8, 24, 256), (256, 12, 8)])
+                               (8, 12, 512), (12, 8, 384), (12, 8, 256), (8, 24, 256), (256, 12, 8),
+                               (192, 12, 8), (12, 192, 192)])
 def test_every_schedule_variant(torch_cuda, prec, tol, n):
     """Every kernel variant the autotuner may pick gives the oracle's result (the last grids put
     pencils of 1024 and 768 points on axes 0 and 1, and rows of 512, 384 and 256 on axis 2: the
     rows of 256 run in blocks of several row groups; the last puts 512-point pencils on axis 0,
-    whose variant 1 in float32 exchanges real and imaginary parts in turn)."""
+    whose variant 1 in float32 exchanges real and imaginary parts in turn; the two after it put
+    384-point pencils on axes 0 and 1 and rows of 192 on axis 2, whose plan 1 ends in radix 24)."""
     from paper_2405_02603_amd import _lib
     torch = torch_cuda
     n3 = W._as3(n, int)
