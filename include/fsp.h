@@ -257,17 +257,20 @@ fsp_status fsp_solve_batched(int count, const fsp_plan* plans, const void* const
 
 /* Schedules for a set of solves launched together (no passage of the paper:
  * how the passes map onto the GPU).  Plans are grouped by grid, precision
- * and layout, whatever their schedules.  For each group on a grid that
- * supports the plane kernels, the group's solves are timed together (reps
- * timed launches of the whole group after a warm one, 1 <= reps <= 8, median)
- * with the separate passes fsp_autotune last found fastest for that grid
- * (else the first plan's), with the plane kernel for passes 0-1, for passes
- * 3-4, and for both, the axis-0 variant as last tuned; the fastest is set on
- * every plan of the group.  Groups whose tuned schedule is the fused slab
- * keep their schedules.  A single solve may prefer another
+ * and layout, whatever their schedules.  Each group's solves are timed
+ * together (reps timed launches of the whole group after a warm one,
+ * 1 <= reps <= 8, median) with the separate passes fsp_autotune last found
+ * fastest for that grid (else the first plan's) and, on a grid that supports
+ * the plane kernels, with the plane kernel for passes 0-1, for passes 3-4,
+ * and for both, the axis-0 variant as last tuned.  From the fastest, each pass
+ * that is not a plane kernel then tries its other variants in turn, each
+ * timed the same way, and keeps one only if the group runs faster.  The
+ * result is set on every plan of the group.  Groups whose tuned schedule is
+ * the fused slab keep their schedules.  A single solve may prefer another
  * schedule than many solves launched together: a plane kernel has one block
- * per plane, too few to fill the GPU for one small grid.  Other groups keep
- * their schedules.  rho[i] and phi[i] as in fsp_solve_batched, phi[i] must not
+ * per plane, too few to fill the GPU for one small grid, and a kernel held
+ * back by its registers gains from the wider launch.  rho[i] and phi[i] as in
+ * fsp_solve_batched, phi[i] must not
  * overlap rho[i] (FSP_ERR_INVALID_ARG): the timed solves write phi.  Plans not
  * ready: FSP_ERR_NOT_READY.  Synchronises `stream`; allocates nothing. */
 fsp_status fsp_autotune_batch(int count, const fsp_plan* plans, const void* const* rho, void* const* phi, int reps,

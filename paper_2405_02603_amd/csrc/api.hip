@@ -1300,25 +1300,19 @@ fsp_status fsp_autotune_batch(int count, const fsp_plan* plans, const void* cons
       if (it != g_tuned.end())
         for (int k = 0; k < 5; ++k) base[k] = it->second[k], sp[k] = it->second[6 + k];
     }
-    if (base[1] == fsp::FUSED || !plane_supported(p0)) continue;  // nothing to choose between
+    if (base[1] == fsp::FUSED) continue;  // the fused slab: nothing to choose between
     std::vector<std::array<int, 5>> orig;
     for (fsp_plan q : gp) orig.push_back({q->var[0], q->var[1], q->var[2], q->var[3], q->var[4]});
-    const int P = fsp::PLANE;
-    const int cand[4][5] = {{sp[0], sp[1], base[2], sp[3], sp[4]},
-                            {P, P, base[2], sp[3], sp[4]},
-                            {sp[0], sp[1], base[2], P, P},
-                            {P, P, base[2], P, P}};
-    float best_ms = 1e30f;
-    int pick = -1;
-    for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+    // median time of the group's solves enqueued together with schedule c
+    auto time_group = [&](const int* c, float* out) {
       for (fsp_plan q : gp)
-        for (int k = 0; k < 5; ++k) q->var[k] = cand[c][k];
+        for (int k = 0; k < 5; ++k) q->var[k] = c[k];
       float rep_ms[8] = {};
       for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // r == 0 warms up
         e = hipEventRecord(e0, s);
         if (e == hipSuccess) {
           st = enqueue_batch((int)gp.size(), gp.data(), gr.data(), gf.data(), &s, 1);
-          if (st != FSP_OK) break;
+          if (st != FSP_OK) return;
         }
         if (e == hipSuccess) e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1326,12 +1320,44 @@ fsp_status fsp_autotune_batch(int count, const fsp_plan* plans, const void* cons
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (r > 0) rep_ms[r - 1] = ms;
       }
-      if (st != FSP_OK) break;
-      const float ms = median_ms(rep_ms, reps);
-      if (e == hipSuccess && ms < best_ms) best_ms = ms, pick = c;
+      *out = median_ms(rep_ms, reps);
+    };
+    const int P = fsp::PLANE;
+    const int cand[4][5] = {{sp[0], sp[1], base[2], sp[3], sp[4]},
+                            {P, P, base[2], sp[3], sp[4]},
+                            {sp[0], sp[1], base[2], P, P},
+                            {P, P, base[2], P, P}};
+    const int ncand = plane_supported(p0) ? 4 : 1;
+    float best_ms = 1e30f;
+    int cur[5] = {cand[0][0], cand[0][1], cand[0][2], cand[0][3], cand[0][4]};
+    bool timed = false;
+    for (int c = 0; c < ncand && e == hipSuccess && st == FSP_OK; ++c) {
+      float ms = 0;
+      time_group(cand[c], &ms);
+      if (e == hipSuccess && st == FSP_OK && ms < best_ms) {
+        best_ms = ms, timed = true;
+        for (int k = 0; k < 5; ++k) cur[k] = cand[c][k];
+      }
+    }
+    // then each separate pass in turn: its other variants, timed with the group
+    // (a variant that wins alone need not win when the group's launches are
+    // wider, e.g. where occupancy decides)
+    for (int q = 0; q < 5 && timed && e == hipSuccess && st == FSP_OK; ++q) {
+      if (cur[q] == P) continue;
+      for (int v = 0; v < fsp::NUM_VARIANTS && e == hipSuccess && st == FSP_OK; ++v) {
+        if (v == cur[q]) continue;
+        int trial[5] = {cur[0], cur[1], cur[2], cur[3], cur[4]};
+        trial[q] = v;
+        float ms = 0;
+        time_group(trial, &ms);
+        if (e == hipSuccess && st == FSP_OK && ms < best_ms) {
+          best_ms = ms;
+          cur[q] = v;
+        }
+      }
     }
     for (size_t m = 0; m < gp.size(); ++m)
-      for (int k = 0; k < 5; ++k) gp[m]->var[k] = pick >= 0 ? cand[pick][k] : orig[m][k];
+      for (int k = 0; k < 5; ++k) gp[m]->var[k] = timed ? cur[k] : orig[m][k];
     if (st != FSP_OK) break;
   }
   if (e0) (void)hipEventDestroy(e0);

@@ -89,9 +89,10 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
 // Axis-0 pass variants: variant 0 as col_cfg, variant 1 as col_cfg or the
 // split-exchange form (conv_split_wpe, below); variant 2 keeps the
 // complete twiddle table in LDS, with the shape of variant 0 (else 1) when the
-// table costs no resident block (conv_twf_fits), and with the split
-// exchanges too where variant 1 has them; else it is the pipelined persistent
-// kernel (grid of at most CONV_PIPE_BLOCKS blocks) with the shape of variant 1.
+// table costs no resident block (conv_twf_fits) or saves registers
+// (conv_twf_wide), and with the split exchanges too where variant 1 has them;
+// else it is the pipelined persistent kernel (grid of at most
+// CONV_PIPE_BLOCKS blocks) with the shape of variant 1.
 constexpr int CONV_PIPE_BLOCKS = 1024;
 constexpr int CONV_GATHER_MIN_BLOCKS = 2048;
 constexpr int CONV_LDS_PER_CU = 163840;
@@ -106,9 +107,17 @@ __host__ __device__ constexpr bool conv_twf_fits(int L, int v) {
   return plan_len(L, c.pid) > 1 && with <= CONV_LDS_PER_CU && CONV_LDS_PER_CU / with == CONV_LDS_PER_CU / base;
 }
 
+// Float32 256-point pencils take the table although it costs a resident
+// block by LDS (5 -> 4 blocks of 32 KB): without the six-power products the
+// kernel needs 111 VGPRs instead of 140, so 4 waves per SIMD reside instead of 3.
+template <typename T>
+__host__ __device__ constexpr bool conv_twf_wide(int L) {
+  return sizeof(T) == 4 && L == 256;
+}
+
 template <typename T>
 __host__ __device__ constexpr bool conv_twf(int L, int v) {
-  return v == 2 && (conv_twf_fits<T>(L, 0) || conv_twf_fits<T>(L, 1));
+  return v == 2 && (conv_twf_fits<T>(L, 0) || conv_twf_fits<T>(L, 1) || conv_twf_wide<T>(L));
 }
 
 template <typename T>
@@ -128,7 +137,7 @@ __host__ __device__ constexpr int conv_split_wpe(int L) {
 
 template <typename T>
 __host__ __device__ constexpr TileCfg conv_cfg(int L, int v) {
-  return conv_twf<T>(L, v) ? col_cfg<T>(L, conv_twf_fits<T>(L, 0) ? 0 : 1)
+  return conv_twf<T>(L, v) ? col_cfg<T>(L, conv_twf_fits<T>(L, 0) || conv_twf_wide<T>(L) ? 0 : 1)
          : conv_pipelined<T>(L, v)                ? col_cfg<T>(L, 1)
          : v == 1 && conv_split_wpe<T>(L) > 0     ? col_cfg<T>(L, 0)
                                                   : col_cfg<T>(L, v);
