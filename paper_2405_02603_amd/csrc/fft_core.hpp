@@ -83,6 +83,29 @@ __host__ __device__ constexpr RadixPlan radix_plan(int L, int pid = 0) {
 
 __host__ __device__ constexpr int plan_len(int L, int pid = 0) { return radix_plan(L, pid).n; }
 
+// A plan is well formed when its radices multiply to L, each has a butterfly
+// (Dft below), and the first is even and divides 32 (pruned first and last
+// stages, constant twiddles).
+__host__ __device__ constexpr bool plan_ok(int L, int pid) {
+  const RadixPlan p = radix_plan(L, pid);
+  if (p.n < 1 || p.n > 4 || p.r[0] % 2 != 0 || 32 % p.r[0] != 0) return false;
+  int prod = 1;
+  for (int i = 0; i < p.n; ++i) {
+    const int r = p.r[i];
+    if (r != 2 && r != 3 && r != 4 && r != 8 && r != 12 && r != 16 && r != 24 && r != 32) return false;
+    prod *= r;
+  }
+  return prod == L;
+}
+__host__ __device__ constexpr bool plans_ok() {
+  constexpr int lengths[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+  for (int L : lengths)
+    for (int pid = 0; pid < NUM_PLANS; ++pid)
+      if (!plan_ok(L, pid)) return false;
+  return true;
+}
+static_assert(plans_ok(), "every radix plan multiplies to its length and starts with an even radix dividing 32");
+
 // Radix of stage s; rev selects the reversed plan used by inverse transforms.
 __host__ __device__ constexpr int plan_radix(int L, int pid, bool rev, int s) {
   return rev ? radix_plan(L, pid).r[radix_plan(L, pid).n - 1 - s] : radix_plan(L, pid).r[s];
