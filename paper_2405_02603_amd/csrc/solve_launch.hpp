@@ -107,12 +107,13 @@ __host__ __device__ constexpr bool conv_twf_fits(int L, int v) {
   return plan_len(L, c.pid) > 1 && with <= CONV_LDS_PER_CU && CONV_LDS_PER_CU / with == CONV_LDS_PER_CU / base;
 }
 
-// Float32 256-point pencils take the table although it costs a resident
-// block by LDS (5 -> 4 blocks of 32 KB): without the six-power products the
-// kernel needs 111 VGPRs instead of 140, so 4 waves per SIMD reside instead of 3.
+// 256-point pencils take the table although it costs a resident block by LDS
+// (5 -> 4 blocks): in float32 the kernel then needs 111 VGPRs instead of 140,
+// so 4 waves per SIMD reside instead of 3; in float64 registers hold 2 waves
+// per SIMD either way, and the table's fewer instructions pay.
 template <typename T>
 __host__ __device__ constexpr bool conv_twf_wide(int L) {
-  return sizeof(T) == 4 && L == 256;
+  return L == 256;
 }
 
 template <typename T>
