@@ -282,7 +282,9 @@ fsp_status fsp_autotune_batch(int count, const fsp_plan* plans, const void* cons
  * fsp_solve_batched and writes their buffers into a device-resident table (one
  * device allocation, owned by the batch); nothing is enqueued.  Solves of equal
  * shape form one launch group, however many there are (up to 65535 per
- * group), and the groups become parallel branches of the graph.  The first
+ * group).  The group that moves the most bytes runs first; the others (up to
+ * eight, the smallest, after any further ones in turn) then run together on
+ * parallel branches of the graph.  The first
  * fsp_batch_launch captures the launches, which read every item's buffers from
  * the table when they run, and launches the graph on `stream`; later calls
  * replay it.  fsp_batch_set_io(b, rho, phi, stream) replaces the rho / phi of

@@ -1392,10 +1392,15 @@ struct fsp_batch_s {
   std::vector<fsp::ItemPtrs> host;  // the table as last written (slot order)
   fsp::ItemPtrs* table = nullptr;   // the device table the captured kernels read
   int device = 0;
-  // graph branches the launch groups are spread over: one (groups in turn,
-  // largest first) measured fastest on the 64-solve mix -- concurrent groups
-  // slow each other's kernels more than they fill idle compute units
+  // Graph layout.  The leading groups (largest first) run in turn on
+  // `branches` branches; the last `tail` groups (the smallest) then run
+  // together, each on a branch of its own, once the leading ones are done.
+  // Measured on the 64-solve mix: the largest group alone first, then the
+  // other four together (0.797 ms; 0.825 ms all in turn, 0.808 ms with the
+  // second largest also in turn).  Groups that overlap the largest slow its
+  // kernels more than they fill idle compute units.
   int branches = 1;
+  int tail = 8;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1426,14 +1431,18 @@ __global__ __launch_bounds__(SET_ITEMS) void k_set_items(SetItemsArgs a) {
 // on parallel branches; every launch reads its items' buffers from the table.
 hipError_t capture_batch(fsp_batch_s* b) {
   const int nb = b->branches;
+  const int ng = (int)b->groups.size();
+  const int nt = std::max(0, std::min(b->tail, ng - 1));  // trailing groups on branches of their own
+  const int ns = nb + nt;
   hipStream_t cs = nullptr;
-  std::vector<hipStream_t> side(nb, nullptr);
+  std::vector<hipStream_t> side(ns, nullptr);
   hipEvent_t fork = nullptr;
-  std::vector<hipEvent_t> join(nb, nullptr);
+  std::vector<hipEvent_t> join(ns, nullptr), mid(nb, nullptr);
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+  for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+  for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+  for (int i = 0; i < nb && nt > 0 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&mid[i], hipEventDisableTiming);
   bool capturing = false;
   if (e == hipSuccess) {
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -1441,15 +1450,22 @@ hipError_t capture_batch(fsp_batch_s* b) {
   }
   if (e == hipSuccess) e = hipEventRecord(fork, cs);
   for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[i], fork, 0);
-  for (size_t k = 0; k < b->groups.size() && e == hipSuccess; ++k) {
+  auto launch_group = [&](int k, hipStream_t st) {
     const fsp_batch_s::Group& gr = b->groups[k];
     fsp::SolveGeom g = group_geom(gr.plan);
     g.items = gr.count;
     g.items_dev = b->table + gr.first;
-    e = run_group(g, gr.plan->d.prec == FSP_F64, 0, 4, side[k % nb]);
+    e = run_group(g, gr.plan->d.prec == FSP_F64, 0, 4, st);
+  };
+  for (int k = 0; k < ng - nt && e == hipSuccess; ++k) launch_group(k, side[k % nb]);
+  if (nt > 0) {  // the trailing groups start together once every leading group is done
+    for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipEventRecord(mid[i], side[i]);
+    for (int t = 0; t < nt && e == hipSuccess; ++t)
+      for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[nb + t], mid[i], 0);
+    for (int t = 0; t < nt && e == hipSuccess; ++t) launch_group(ng - nt + t, side[nb + t]);
   }
-  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipEventRecord(join[i], side[i]);
-  for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(cs, join[i], 0);
+  for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipEventRecord(join[i], side[i]);
+  for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipStreamWaitEvent(cs, join[i], 0);
   if (capturing) {
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -1462,6 +1478,8 @@ hipError_t capture_batch(fsp_batch_s* b) {
     }
   }
   for (auto ev : join)
+    if (ev) (void)hipEventDestroy(ev);
+  for (auto ev : mid)
     if (ev) (void)hipEventDestroy(ev);
   if (fork) (void)hipEventDestroy(fork);
   for (auto st : side)
@@ -1528,6 +1546,7 @@ fsp_status fsp_batch_create(int count, const fsp_plan* plans, const void* const*
     return model_bytes(x.plan) * x.count > model_bytes(y.plan) * y.count;
   });
   if (const char* env = std::getenv("FSP_BATCH_BRANCHES")) b->branches = std::max(1, std::min(16, std::atoi(env)));
+  if (const char* env = std::getenv("FSP_BATCH_TAIL")) b->tail = std::max(0, std::min(8, std::atoi(env)));
   DeviceGuard guard;
   hipError_t e = guard.enter(b->device);
   if (e == hipSuccess) e = hipMalloc(&b->table, b->host.size() * sizeof(fsp::ItemPtrs));
