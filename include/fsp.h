@@ -284,7 +284,8 @@ fsp_status fsp_autotune_batch(int count, const fsp_plan* plans, const void* cons
  * shape form one launch group, however many there are (up to 65535 per
  * group).  The group that moves the most bytes runs first; the others (up to
  * eight, the smallest, after any further ones in turn) then run together on
- * parallel branches of the graph.  The first
+ * three parallel branches of the graph, each group (largest first) on the
+ * branch with the fewest bytes so far.  The first
  * fsp_batch_launch captures the launches, which read every item's buffers from
  * the table when they run, and launches the graph on `stream`; later calls
  * replay it.  fsp_batch_set_io(b, rho, phi, stream) replaces the rho / phi of

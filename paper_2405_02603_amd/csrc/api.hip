@@ -1394,13 +1394,15 @@ struct fsp_batch_s {
   int device = 0;
   // Graph layout.  The leading groups (largest first) run in turn on
   // `branches` branches; the last `tail` groups (the smallest) then run
-  // together, each on a branch of its own, once the leading ones are done.
-  // Measured on the 64-solve mix: the largest group alone first, then the
-  // other four together (0.797 ms; 0.825 ms all in turn, 0.808 ms with the
-  // second largest also in turn).  Groups that overlap the largest slow its
-  // kernels more than they fill idle compute units.
+  // together on `tail_branches` branches, each group (largest first) put on
+  // the branch with the fewest model bytes so far, once the leading ones are
+  // done.  Measured on the 64-solve mix: the largest group alone first, then
+  // the other four on three branches (0.792 ms; 0.798 on four, 0.802 on two,
+  // 0.827 all in turn, 0.851 all five side by side).  Groups that overlap
+  // the largest slow its kernels more than they fill idle compute units.
   int branches = 1;
   int tail = 8;
+  int tail_branches = 3;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -1432,8 +1434,9 @@ __global__ __launch_bounds__(SET_ITEMS) void k_set_items(SetItemsArgs a) {
 hipError_t capture_batch(fsp_batch_s* b) {
   const int nb = b->branches;
   const int ng = (int)b->groups.size();
-  const int nt = std::max(0, std::min(b->tail, ng - 1));  // trailing groups on branches of their own
-  const int ns = nb + nt;
+  const int nt = std::max(0, std::min(b->tail, ng - 1));  // trailing groups
+  const int ntb = std::max(0, std::min(nt, b->tail_branches));  // their branches
+  const int ns = nb + ntb;
   hipStream_t cs = nullptr;
   std::vector<hipStream_t> side(ns, nullptr);
   hipEvent_t fork = nullptr;
@@ -1460,9 +1463,15 @@ hipError_t capture_batch(fsp_batch_s* b) {
   for (int k = 0; k < ng - nt && e == hipSuccess; ++k) launch_group(k, side[k % nb]);
   if (nt > 0) {  // the trailing groups start together once every leading group is done
     for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipEventRecord(mid[i], side[i]);
-    for (int t = 0; t < nt && e == hipSuccess; ++t)
+    for (int t = 0; t < ntb && e == hipSuccess; ++t)
       for (int i = 0; i < nb && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[nb + t], mid[i], 0);
-    for (int t = 0; t < nt && e == hipSuccess; ++t) launch_group(ng - nt + t, side[nb + t]);
+    // each (largest first) to the branch with the fewest model bytes so far
+    std::vector<double> load(ntb, 0.0);
+    for (int k = ng - nt; k < ng && e == hipSuccess; ++k) {
+      const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[t] += model_bytes(b->groups[k].plan) * b->groups[k].count;
+      launch_group(k, side[nb + t]);
+    }
   }
   for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipEventRecord(join[i], side[i]);
   for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipStreamWaitEvent(cs, join[i], 0);
@@ -1547,6 +1556,7 @@ fsp_status fsp_batch_create(int count, const fsp_plan* plans, const void* const*
   });
   if (const char* env = std::getenv("FSP_BATCH_BRANCHES")) b->branches = std::max(1, std::min(16, std::atoi(env)));
   if (const char* env = std::getenv("FSP_BATCH_TAIL")) b->tail = std::max(0, std::min(8, std::atoi(env)));
+  if (const char* env = std::getenv("FSP_BATCH_TAIL_BRANCHES")) b->tail_branches = std::max(1, std::min(8, std::atoi(env)));
   DeviceGuard guard;
   hipError_t e = guard.enter(b->device);
   if (e == hipSuccess) e = hipMalloc(&b->table, b->host.size() * sizeof(fsp::ItemPtrs));
