@@ -72,8 +72,8 @@ __host__ __device__ constexpr TileCfg row_cfg(int LC, int v) {
     case 32: return v == 0 ? TileCfg{0, 32, 4} : v == 1 ? TileCfg{1, 32, 2} : TileCfg{0, 16, 8};
     case 48: return v == 0 ? TileCfg{0, d ? 32 : 64, 1} : v == 1 ? TileCfg{1, 32, 4} : TileCfg{0, 32, 3};
     case 64: return v == 0 ? TileCfg{0, 32, 8} : v == 1 ? TileCfg{1, 32, 4} : TileCfg{0, 16, 8};
-    case 96: return v == 0 ? TileCfg{0, 32, 4} : v == 1 ? TileCfg{1, 32, 4} : TileCfg{0, 16, 8};
-    // 128: variant 2 with 16 threads a row, 128-byte row segments per wave (wide batched launches)
+    // 96 and 128: a variant with 16 threads a row, 128-byte row segments per wave
+    case 96: return v == 0 ? TileCfg{0, 32, 4} : v == 1 ? TileCfg{0, 8, 16} : TileCfg{0, 16, 8};
     case 128: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 8} : TileCfg{1, 8, 16};
     case 192: return v == 0 ? TileCfg{0, d ? 8 : 16, 8} : v == 1 ? TileCfg{1, 16, 8} : TileCfg{0, 8, 16};
     // 256 in float32: small blocks of 4 rows, 2-4 groups each (more bytes in flight a thread)
